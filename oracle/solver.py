@@ -1,0 +1,133 @@
+"""Projective-dynamics time stepping for one cell and for a suspension (FP64).
+
+Test infrastructure only (see the package docstring).
+
+One implicit step from (x_n, v_n) under external nodal forces f_n (the
+elastodynamics equation, eq. 2, with lumped vertex mass m and body force
+standing in for the fluid coupling, Introduction; forces in, positions and
+velocities out as in the fluid-solid exchange, Implementation and
+architecture):
+
+    s = x_n + h v_n + (h^2/m) f_n,   q = s
+    repeat n_iter times:
+        local step:  projections P(q) (``projections.local_step``)
+        global step: A q = (m/h^2) s + sum_t A_t G_t (w_s Ps_t^T + w_a Pa_t^T)
+                           + sum_e w_b c_e K_e (x) Pb_e + w_v Pv
+    x_{n+1} = q,   v_{n+1} = (q - x_n) / h
+
+The diagnostic energy at iterate q (with P = P(q)) is
+    E(q) = (m/2h^2)|q - s|^2 + sum_t (A_t/2)[w_s |F - Ps|^2 + w_a |F - Pa|^2]
+           + sum_e (w_b c_e/2)|y - Pb|^2 + (w_v/2)|q - Pv|^2,
+which the alternation never increases.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.linalg
+
+from . import operators as ops_mod
+from . import projections as proj
+
+
+@dataclass
+class Params:
+    weights: tuple  # (w_stretch, w_area, w_bend, w_volume)
+    mass: float
+    dt: float
+
+
+def rhs(o: ops_mod.CellOperators, P: dict, s: np.ndarray, prm: Params) -> np.ndarray:
+    ws, wa, wb, wv = prm.weights
+    b = (prm.mass / prm.dt ** 2) * s
+    # triangles: rows of A_t G_t (w_s Ps^T + w_a Pa^T) go to the triangle's vertices
+    Wt = o.area[:, None, None] * (ws * P["Ps"] + wa * P["Pa"])  # [F, 3xyz, 2]
+    contrib = np.einsum("frk,fdk->frd", o.G, Wt)  # [F, 3 vertices, 3 xyz]
+    for r in range(3):
+        np.add.at(b, o.tris[:, r], contrib[:, r, :])
+    # hinges: w_b c_e K_e[r] Pb_e to vertex H_e[r]
+    hb = (wb * o.c)[:, None, None] * o.K[:, :, None] * P["Pb"][:, None, :]  # [E, 4, 3]
+    for r in range(4):
+        np.add.at(b, o.H[:, r], hb[:, r, :])
+    b += wv * P["Pv"]
+    return b
+
+
+def energy(o: ops_mod.CellOperators, q: np.ndarray, s: np.ndarray, P: dict, prm: Params) -> float:
+    ws, wa, wb, wv = prm.weights
+    e = 0.5 * prm.mass / prm.dt ** 2 * np.sum((q - s) ** 2)
+    dF_s = np.sum((P["F"] - P["Ps"]) ** 2, axis=(1, 2))
+    dF_a = np.sum((P["F"] - P["Pa"]) ** 2, axis=(1, 2))
+    e += np.sum(0.5 * o.area * (ws * dF_s + wa * dF_a))
+    e += np.sum(0.5 * wb * o.c * np.sum((P["y"] - P["Pb"]) ** 2, axis=1))
+    e += 0.5 * wv * np.sum((q - P["Pv"]) ** 2)
+    return float(e)
+
+
+class CellSolver:
+    """Factorised system for one (mesh class, weights, mass, dt)."""
+
+    def __init__(self, o: ops_mod.CellOperators, prm: Params):
+        self.o = o
+        self.prm = prm
+        self.A = ops_mod.system_matrix(o, prm.weights, prm.mass, prm.dt)
+        self.chol = ops_mod.factor(self.A)
+
+    def step(self, x, v, f, n_iter, record_energy=False):
+        """One time step; returns (x_new, v_new, energies) with energies
+        E(q^0..q^n_iter) when requested."""
+        h, m = self.prm.dt, self.prm.mass
+        s = x + h * v + (h * h / m) * f
+        q = s.copy()
+        energies = []
+        for _ in range(n_iter):
+            P = proj.local_step(q, self.o)
+            if record_energy:
+                energies.append(energy(self.o, q, s, P, self.prm))
+            b = rhs(self.o, P, s, self.prm)
+            q = scipy.linalg.cho_solve(self.chol, b)
+        if record_energy:
+            P = proj.local_step(q, self.o)
+            energies.append(energy(self.o, q, s, P, self.prm))
+        return q, (q - x) / h, energies
+
+    def rollout(self, x0, v0, f, n_iter, n_steps, forces_per_step=None):
+        x, v = x0.copy(), v0.copy()
+        for n in range(n_steps):
+            fn = f if forces_per_step is None else forces_per_step[n]
+            x, v, _ = self.step(x, v, fn, n_iter)
+        return x, v
+
+
+_OPS_CACHE: dict = {}
+
+
+def operators_for(mesh_class) -> ops_mod.CellOperators:
+    key = id(mesh_class)
+    o = _OPS_CACHE.get(key)
+    if o is None or o.X is not mesh_class.rest:
+        o = ops_mod.build_operators(mesh_class.rest, mesh_class.tris)
+        _OPS_CACHE[key] = o
+    return o
+
+
+def run_cell(susp, c: int, n_steps=None, n_iter=None, dt=None):
+    """Roll out one cell of a suspension; returns (x [N,3], v [N,3]) local coords."""
+    mc, x0, v0, f, w = susp.cell_arrays(c)
+    o = operators_for(mc)
+    prm = Params(tuple(w), mc.mass, susp.dt if dt is None else dt)
+    solver = CellSolver(o, prm)
+    return solver.rollout(x0, v0, f, susp.n_iter if n_iter is None else n_iter,
+                          susp.n_steps if n_steps is None else n_steps)
+
+
+def run_cells(susp, cells, n_steps=None, n_iter=None):
+    """Roll out the listed cells; returns {cell: (x, v)}."""
+    return {int(c): run_cell(susp, int(c), n_steps, n_iter) for c in cells}
+
+
+def rel_position_error(x: np.ndarray, x_ref: np.ndarray) -> float:
+    """max_v |x - x_ref| / R with R = max_v |x_ref_v - centroid(x_ref)|."""
+    R = np.linalg.norm(x_ref - x_ref.mean(axis=0), axis=1).max()
+    return float(np.linalg.norm(x - x_ref, axis=1).max() / R)
