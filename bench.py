@@ -1,0 +1,233 @@
+"""Throughput of the batched projective-dynamics step on one MI355X.
+
+One "step" is one implicit time step of every cell: predict, n_iter x (local
+step + global GEMM), update. Default workload: 4096 RBCs (642 vertices each,
+Evans-Fung shape, random rotations on a 10 um lattice, shear + noise forces),
+FP32, 10 PD iterations per step, dt = 1e-4.
+
+Prints ONE JSON line: cell-PD-iterations per second over K timed steps
+(inputs resident in HBM, hipGraph replays), the roofline position of the
+dominant kernel (per-kernel HIP events in a second, eagerly launched pass over
+the same steps), the FP64 oracle timed on host cores on a bounded sample of
+cells, and the relative position error of those cells against the oracle.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rbc_lattice]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "cell-PD-iterations/sec at ≤1e-6 rel err vs FP64; fwd+bwd time; roofline %"
+PEAK = {  # MI355X published peaks
+    "hbm_GBs": 8000.0,
+    "fp32_matrix_TF": 157.3,
+    "fp64_matrix_TF": 78.6,
+    "bf16_matrix_TF": 2500.0,
+    "fp16_matrix_TF": 2500.0,
+    "fp32_vector_TF": 157.3,
+}
+DTYPE = {"fp32": "f32", "fp64": "f64", "bf16": "bf16+f32", "fp16": "f16+f32"}
+
+
+def build_workload(name, cells):
+    from npfem_workload import suspensions as W
+    if name == "rbc_lattice":
+        s = W.rbc_lattice(n_cells=cells or 4096)
+        desc = f"{s.n_cells} RBC x 642 vertices (Evans-Fung, icosphere L3), 10 um lattice, shear+noise forces"
+    elif name == "uneven":
+        s = W.uneven()
+        desc = "3000 RBC (642 v) + 600 platelets (162 v) + 64 large cells (2562 v), weights +-20%"
+    elif name == "precision":
+        s = W.precision_sweep()
+        desc = "16384 RBC (642 v) + 1638 platelets (162 v)"
+    elif name == "single_rbc":
+        s = W.single_rbc()
+        desc = "1 RBC x 162 vertices"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return s, desc
+
+
+def round_inputs(s, precision):
+    from npfem_workload.suspensions import Suspension
+    if precision == "fp64":
+        return s
+    r = lambda a: a.astype(np.float32).astype(np.float64)
+    return Suspension(s.classes, s.cell_class, s.origins, r(s.x0), r(s.v0), r(s.forces),
+                      r(s.weights), s.dt, s.n_iter, s.n_steps, s.name, dict(s.extra))
+
+
+def _oracle_cell(args):
+    """Worker: roll one cell out with the oracle, single-threaded BLAS."""
+    susp, c, n_steps = args
+    from oracle import solver as S
+    t0 = time.perf_counter()
+    x, v = S.run_cell(susp, c, n_steps=n_steps)
+    return c, x, time.perf_counter() - t0
+
+
+def cpu_baseline(susp, cells, n_steps):
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(len(cells), initializer=_pin_threads) as pool:
+        res = pool.map(_oracle_cell, [(susp, int(c), n_steps) for c in cells])
+    wall = time.perf_counter() - t0
+    return {c: x for c, x, _ in res}, wall, sum(t for _, _, t in res)
+
+
+def _pin_threads():
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+
+
+def algorithmic_work(s):
+    """Per-launch algorithmic work of the global GEMM (dense 2 N^2 per column)."""
+    flops = 0.0
+    for k, mc in enumerate(s.classes):
+        n_c = int((s.cell_class == k).sum())
+        flops += 2.0 * mc.n_verts ** 2 * 3 * n_c
+    return flops
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rbc_lattice")
+    ap.add_argument("--cells", type=int, default=0)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16", "fp16"])
+    ap.add_argument("--n-iter", type=int, default=10)
+    ap.add_argument("--cpu-cells", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py: this build measures one GPU only (the per-cell step needs no "
+              "exchange between GPUs); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2011_04332_amd import solver
+    from npfem_workload import suspensions as W
+
+    s, desc = build_workload(a.workload, a.cells)
+    s = round_inputs(s, a.precision)
+    dt, n_iter = s.dt, a.n_iter
+    print(f"[bench] workload {a.workload}: {desc}; {a.precision}; steps {a.steps} warmup {a.warmup}",
+          file=sys.stderr, flush=True)
+
+    b, pos, vel, f, meshes = solver.batch_from_suspension(s, precision=a.precision)
+    x_init, v_init = pos.clone(), vel.clone()
+    for _ in range(a.warmup):
+        b.step(f, dt, n_iter)
+    b.sync_status()
+    pos.copy_(x_init)
+    vel.copy_(v_init)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        b.step(f, dt, n_iter)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    b.sync_status()
+    elapsed = t1 - t0
+    cell_its = s.n_cells * n_iter * a.steps
+    value = cell_its / elapsed
+    x_timed = pos.clone()
+    print(f"[bench] timed: {elapsed * 1e3:.1f} ms, {value:.4g} cell-it/s", file=sys.stderr, flush=True)
+
+    # second pass over the same steps, launched one by one with HIP events
+    roof, kt, snap = None, None, None
+    cpu_steps = min(a.cpu_steps, a.steps)
+    if not a.no_kernel_timing:
+        pos.copy_(x_init)
+        vel.copy_(v_init)
+        bt = solver.Batch(meshes, s.cell_class, pos, vel,
+                          cell_weights=None if s.uniform_weights() else s.weights,
+                          precision=a.precision, kernel_timing=True)
+        for i in range(a.steps):
+            bt.step(f, dt, n_iter)
+            if i + 1 == cpu_steps:
+                snap = pos.double().cpu().numpy()
+        kt = bt.kernel_times()
+        bt.sync_status()
+        bitwise = bool(torch.equal(pos, x_timed))
+        bt.close()
+        dom = max(("local", "global"), key=lambda k: kt[k][0])
+        g_ms, g_n = kt["global"]
+        flops = algorithmic_work(s)
+        gemm_avg_s = g_ms / g_n * 1e-3
+        peak_tf = PEAK[f"{a.precision}_matrix_TF"]
+        achieved_tf = flops / gemm_avg_s / 1e12
+        roof = {
+            "bound": "mfma",
+            "kernel": "global-step GEMM (gemm_kernel)",
+            "achieved": round(achieved_tf, 3),
+            "peak": peak_tf,
+            "unit": "TFLOP/s",
+            "frac": round(achieved_tf / peak_tf, 4),
+            "traffic": None,
+            "avg_launch_us": round(gemm_avg_s * 1e6, 2),
+            "dominant_kernel": dom,
+            "kernel_ms_per_step": {k: round(v[0] / a.steps, 4) for k, v in kt.items()},
+            "timing_pass_bitwise_equal": bitwise,
+        }
+        print(f"[bench] kernel times (ms/step): {roof['kernel_ms_per_step']}", file=sys.stderr,
+              flush=True)
+
+    cpu, parity = None, None
+    if not a.no_cpu_baseline and snap is not None:
+        ncores = min(a.cpu_cells, os.cpu_count() or 1, 16)
+        cells = W.sample_cells(s, [ncores])[:ncores]
+        ref, wall, cpu_s = cpu_baseline(s, cells, cpu_steps)
+        ci = len(cells) * cpu_steps * n_iter
+        cpu = {"value": round(ci / wall, 3), "unit": "cell-PD-iterations/s", "cores": int(ncores),
+               "kind": "oracle",
+               "sample": f"{len(cells)} sampled cells x {cpu_steps} steps x {n_iter} PD iterations, "
+                         f"one process per cell, FP64 numpy/scipy, wall {wall:.1f} s"}
+        from oracle import solver as S
+        errs = [S.rel_position_error(snap[:, s.cell_slice(c)].T, x) for c, x in ref.items()]
+        parity = {"max_rel_pos_err": float(max(errs)), "cells": [int(c) for c in cells],
+                  "steps": cpu_steps, "bound": 1e-6 if a.precision == "fp32" else 1e-5}
+        print(f"[bench] oracle: {cpu['value']} cell-it/s on {ncores} cores; parity {parity}",
+              file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "cell-PD-iterations/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(elapsed / a.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[a.precision],
+        "data": "synthetic",
+        "config": {"workload": f"{a.workload}: {desc}", "cells": s.n_cells, "pd_iterations": n_iter,
+                   "dt": dt, "precision": a.precision},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+    b.close()
+
+
+if __name__ == "__main__":
+    main()

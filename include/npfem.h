@@ -1,0 +1,199 @@
+/*
+ * npfem.h - C ABI of the batched projective-dynamics membrane solver for
+ * MI355X (gfx950).
+ *
+ * The library advances many deformable blood cells (closed triangulated
+ * membranes) by implicit time steps of the elastodynamics equation (eq. 2:
+ * rho0 phi'' = div P + rho0 b) discretised as a mass-lumped linear
+ * finite-element membrane (Introduction) and integrated with projective
+ * dynamics, the scheme the solid solver derives from (Implementation and
+ * architecture). The fluid and the immersed-boundary coupling are outside
+ * the library: the caller supplies external nodal forces and receives
+ * positions and velocities, which is the data the fluid-solid exchange
+ * carries (Implementation and architecture). Like the stand-alone solver
+ * library driven from Python through ctypes (section "Rhino-Grasshopper
+ * environment"), the calls are: load meshes with a material, build a batch,
+ * add forces and run steps.
+ *
+ * One step, per cell, with lumped vertex mass m and time step h:
+ *   s = x + h v + (h^2/m) f;  q = s
+ *   repeat n_iter: local step (projections of every elemental potential),
+ *                  global step  A q = (m/h^2) s + sum_i w_i S_i^T P_i
+ *   x <- q;  v <- (q - x_old)/h
+ * with A = (m/h^2) I + (w_s + w_a) sum_t A_t G_t G_t^T
+ *        + w_b sum_e c_e K_e K_e^T + w_v I
+ * (per-triangle strain and area, per-hinge bending, per-cell volume; the
+ * body energy is the weighted sum of elemental potentials, section "Setting
+ * up new materials").
+ *
+ * Conventions
+ *  - Every function returns NPFEM_OK (0) or a negative NPFEM_ERR_* code; the
+ *    thread-local message of the last failure is npfem_last_error(). No C++
+ *    exception crosses the ABI.
+ *  - Per-vertex device arrays are SoA [3][sum_N]: all x, then all y, then all
+ *    z, cells class-major then cell-major. Element type is double for
+ *    NPFEM_FP64 and float for every other precision.
+ *  - Positions are cell-local: relative to an origin per cell that the caller
+ *    keeps (in FP64 if it wants). The step is translation-equivariant, so the
+ *    library never needs the origin; keeping coordinates small keeps FP32
+ *    rounding at the scale of the cell, not of the domain.
+ *  - Device buffers passed in (positions, velocities, forces, gradients) are
+ *    owned by the caller and must outlive the batch. The library copies mesh
+ *    data and owns its operators, workspace and graphs.
+ *  - All device work of a batch is ordered on the stream given at creation;
+ *    calls return without synchronising unless documented otherwise.
+ *  - A batch is not thread-safe: one host thread at a time per batch.
+ */
+#ifndef NPFEM_H
+#define NPFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NPFEM_ABI_VERSION 1
+
+enum npfem_status {
+  NPFEM_OK = 0,
+  NPFEM_ERR_INVALID_ARG = -1,    /* bad pointer, size, order or option */
+  NPFEM_ERR_MESH_OPEN = -2,      /* an edge has only one incident triangle */
+  NPFEM_ERR_MESH_NONMANIFOLD = -3, /* edge used twice in one direction, >2 triangles, bad Euler characteristic */
+  NPFEM_ERR_DEGENERATE_TRI = -4, /* zero-area rest triangle or repeated vertex */
+  NPFEM_ERR_NOT_SPD = -5,        /* non-positive pivot in the FP64 factorisation */
+  NPFEM_ERR_NONFINITE = -6,      /* NaN or Inf seen in state, forces or a reduction */
+  NPFEM_ERR_HIP = -7,            /* HIP runtime error */
+  NPFEM_ERR_OOM = -8             /* device or host allocation failed */
+};
+
+typedef enum npfem_precision {
+  NPFEM_FP64 = 0,        /* state, local step and global step in FP64 */
+  NPFEM_FP32 = 1,        /* FP32 state and kernels, FP32 MFMA global step */
+  NPFEM_BF16_REFINE = 2, /* FP32 state; global step on BF16 MFMA (FP32 accumulate) + refinement */
+  NPFEM_FP16_REFINE = 3  /* as above with FP16 MFMA operands */
+} npfem_precision;
+
+/* Nominal material of a mesh class: constraint weights and lumped mass per
+ * vertex (units are the caller's; the bundled workloads use um, s and
+ * consistent force units). */
+typedef struct npfem_material {
+  double w_stretch; /* strain potential weight (times rest triangle area) */
+  double w_area;    /* area-preservation weight (times rest triangle area) */
+  double w_bend;    /* hinge bending weight (times 3/(A1+A2)) */
+  double w_volume;  /* cell volume-preservation weight (per vertex) */
+  double vertex_mass;
+} npfem_material;
+
+#define NPFEM_OPT_ENERGY 1u     /* record per-cell FP64 energy of every PD iterate of the last step */
+#define NPFEM_OPT_NO_GRAPH 2u   /* launch kernels one by one instead of replaying a captured hipGraph */
+#define NPFEM_OPT_AUTOTUNE 4u   /* time candidate tile shapes per mesh class at the first step */
+#define NPFEM_OPT_SYNC_CHECK 8u /* npfem_step synchronises and reports NONFINITE itself */
+#define NPFEM_OPT_KERNEL_TIMING 16u /* launch one by one with a HIP event pair around every
+                                       kernel; read with npfem_kernel_times */
+
+/* Kernel kinds reported by npfem_kernel_times. */
+enum npfem_kernel_kind {
+  NPFEM_KERNEL_PREDICT = 0,  /* start of step: inertia term and first iterate */
+  NPFEM_KERNEL_LOCAL = 1,    /* local step + right-hand-side gather */
+  NPFEM_KERNEL_GLOBAL = 2,   /* global-step GEMM (first solve and corrections) */
+  NPFEM_KERNEL_RESIDUAL = 3, /* refinement residual */
+  NPFEM_KERNEL_UPDATE = 4,   /* end of step: positions and velocities */
+  NPFEM_KERNEL_KINDS = 5
+};
+
+typedef struct npfem_options {
+  int32_t precision;    /* npfem_precision */
+  int32_t n_refine;     /* correction sweeps after each global solve; -1 = automatic */
+  int32_t max_vol_iter; /* cap on volume-projection sub-iterations; 0 = default */
+  uint32_t flags;       /* NPFEM_OPT_* */
+  void* stream;         /* hipStream_t for all work of the batch; NULL = null stream */
+} npfem_options;
+
+typedef struct npfem_mesh_s* npfem_mesh;
+typedef struct npfem_batch_s* npfem_batch;
+
+/* Host-only. Validates and copies one mesh class and precomputes its rest
+ * operators in FP64: per-triangle G_t (3x2) and area, per-hinge cotangent
+ * stencil K_e, weight c_e and rest magnitude, rest volume, vertex incidence
+ * lists and the sparse Laplacians.
+ *   rest_xyz  host [n_verts][3] rest shape (also the default initial shape)
+ *   tris      host [n_tris][3] vertex indices, counter-clockwise seen from
+ *             outside (positive enclosed volume)
+ *   mat       nominal material
+ * Errors: INVALID_ARG (NULL, n_verts < 4, n_verts > 65535, index out of
+ * range, non-finite or non-positive weights/mass, negative volume),
+ * MESH_OPEN, MESH_NONMANIFOLD, DEGENERATE_TRI, OOM. */
+int npfem_create_mesh(const double* rest_xyz, int32_t n_verts, const int32_t* tris,
+                      int32_t n_tris, const npfem_material* mat, npfem_mesh* out);
+
+/* Host-only queries of a mesh (any output pointer may be NULL). */
+int npfem_mesh_info(npfem_mesh m, int32_t* n_verts, int32_t* n_tris, int32_t* n_hinges,
+                    double* rest_volume);
+
+/* Host-only: the dense FP64 system matrix A (row-major [n_verts][n_verts])
+ * for the given weights (host [4]: stretch, area, bend, volume; NULL =
+ * nominal) and time step. For inspection and tests. */
+int npfem_mesh_system_matrix(npfem_mesh m, const double* weights4, double dt, double* A_out);
+
+/* Builds a batch of n_cells cells over n_meshes mesh classes and binds the
+ * caller's state buffers.
+ *   meshes        host [n_meshes]
+ *   cell_mesh     host [n_cells] class index per cell, non-decreasing
+ *   cell_weights  host [n_cells][4] per-cell (stretch, area, bend, volume)
+ *                 weights, or NULL for each class's nominal material
+ *   pos, vel      device SoA [3][sum_N] (double for NPFEM_FP64, else float),
+ *                 updated in place by npfem_step
+ *   opt           options (NULL = FP32, defaults)
+ * Allocates device workspace; the FP64 factorisation happens at the first
+ * step (it depends on the time step). Errors: INVALID_ARG, HIP, OOM. */
+int npfem_create_batch(const npfem_mesh* meshes, int32_t n_meshes, const int32_t* cell_mesh,
+                       int32_t n_cells, const double* cell_weights, void* pos, void* vel,
+                       const npfem_options* opt, npfem_batch* out);
+
+/* Advances every cell by one implicit step of length dt with n_iter
+ * local/global iterations under constant external nodal forces.
+ *   ext_forces  device SoA [3][sum_N], element type as pos
+ * The first call, and any call with a dt different from the previous one,
+ * rebuilds the system matrices, inverts them in FP64 on the GPU and
+ * re-captures the step graph (synchronous, slow). Otherwise the call only
+ * enqueues work on the batch stream. Non-finite inputs set a device flag read
+ * by npfem_sync_status (or returned here with NPFEM_OPT_SYNC_CHECK).
+ * Errors: INVALID_ARG (dt <= 0 or not finite, n_iter < 1 or > 1000), NOT_SPD,
+ * NONFINITE (only with NPFEM_OPT_SYNC_CHECK), HIP, OOM. */
+int npfem_step(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter);
+
+/* Synchronises the batch stream, returns NPFEM_ERR_NONFINITE if any kernel
+ * saw a NaN/Inf (in state, forces, or a per-cell FP64 reduction) since the
+ * previous call, and clears the flag. */
+int npfem_sync_status(npfem_batch b);
+
+/* Synchronises and copies to host the per-cell FP64 energy E(q^k) of the PD
+ * iterates k = 0 .. n_iter-1 of the last step, layout [n_iter][n_cells].
+ * Requires NPFEM_OPT_ENERGY. capacity = number of doubles host_out holds. */
+int npfem_get_energy(npfem_batch b, double* host_out, int32_t capacity, int32_t* n_iter_out);
+
+/* Synchronises and writes the FP64 enclosed volume of every cell's current
+ * positions into host [n_cells]. */
+int npfem_get_volume(npfem_batch b, double* host_out);
+
+/* Requires NPFEM_OPT_KERNEL_TIMING. Synchronises, converts every event pair
+ * recorded since the last call into elapsed milliseconds and adds them to
+ * running totals per kernel kind; writes the totals (host [NPFEM_KERNEL_KINDS]
+ * ms and launch counts, either may be NULL). reset != 0 clears the totals
+ * after reading. */
+int npfem_kernel_times(npfem_batch b, double* ms_out, int64_t* launches_out, int32_t reset);
+
+/* Releases a mesh or a batch (the handle type is recorded in the object);
+ * NULL is accepted. A mesh may be freed once the batches built on it are
+ * created (they copy what they need). */
+int npfem_free(void* handle);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* npfem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NPFEM_H */

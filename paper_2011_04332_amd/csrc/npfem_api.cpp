@@ -1,0 +1,829 @@
+// C ABI of the batched projective-dynamics solver: argument checks, batch
+// layout, one-time FP64 factorisation on the GPU, per-step kernel sequence
+// and its hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "mesh_ops.h"
+#include "npfem.h"
+#include "npfem_internal.h"
+
+using namespace npfem;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory)
+    return fail(NPFEM_ERR_OOM, "%s: out of device memory", what);
+  return fail(NPFEM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                 \
+  do {                                      \
+    hipError_t e_ = (expr);                 \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+constexpr uint32_t kMeshTag = 0x6e704d31u;   // "npM1"
+constexpr uint32_t kBatchTag = 0x6e704231u;  // "npB1"
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct npfem_mesh_s {
+  uint32_t tag = kMeshTag;
+  npfem_material mat{};
+  MeshOps ops;
+};
+
+namespace {
+
+struct ClassState {
+  MeshOps ops;                 // copy of the class operators
+  npfem_material mat{};
+  int N = 0, Npad = 0, F = 0, E = 0;
+  int n_cells = 0, cell0 = 0;
+  long long col0 = 0, elem0 = 0, vert0 = 0;
+  std::vector<void*> dev;      // device arrays of the class view
+  void* view_ptrs[19] = {};    // device pointers (see upload_class)
+  void* op = nullptr;          // stored global-step operator [Npad][Npad]
+  double beta = 0.0;           // split scale (low precision)
+  int local_block = 256;
+  int gemm_tile = 3;
+};
+
+}  // namespace
+
+struct npfem_batch_s {
+  uint32_t tag = kBatchTag;
+  int device = 0;
+  int precision = NPFEM_FP32;
+  bool fp64 = false;
+  int gemm_kind = 0;  // 0 FP32, 1 FP64, 2 BF16, 3 FP16
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  uint32_t flags = 0;
+  int n_refine_opt = -1;
+  int max_vol_iter = 0;
+  std::vector<ClassState> cls;
+  int n_cells = 0;
+  long long sumN = 0, total_cols = 0, total_elems = 0;
+  void* pos = nullptr;
+  void* vel = nullptr;
+  void* delta = nullptr;
+  void* cterm = nullptr;
+  void* rhs = nullptr;
+  void* res = nullptr;
+  float* colmax = nullptr;
+  int* status = nullptr;
+  double* energy = nullptr;
+  int energy_cap = 0;    // iterations the energy buffer holds
+  int energy_iters = 0;  // iterations recorded by the last step
+  double* volume_buf = nullptr;
+  void* weights_dev = nullptr;
+  bool per_cell = false;
+  std::vector<double> weights_host;  // [n_cells][4] effective weights
+  double dt = -1.0;
+  int n_refine = 0;
+  hipGraphExec_t graph = nullptr;
+  const void* graph_forces = nullptr;
+  int graph_iters = 0;
+  std::vector<void*> allocs;
+  // kernel timing (NPFEM_OPT_KERNEL_TIMING): event pairs around launches
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_pending;  // (kind, start event index)
+  size_t ev_used = 0;
+  double kt_ms[NPFEM_KERNEL_KINDS] = {};
+  long long kt_n[NPFEM_KERNEL_KINDS] = {};
+
+  int ev_begin(hipStream_t st) {
+    if (ev_used + 2 > ev_pool.size()) {
+      for (int i = 0; i < 2; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        ev_pool.push_back(e);
+      }
+    }
+    const int idx = (int)ev_used;
+    ev_used += 2;
+    if (hipEventRecord(ev_pool[idx], st) != hipSuccess) return -1;
+    return idx;
+  }
+  void ev_end(int idx, int kind, hipStream_t st) {
+    if (hipEventRecord(ev_pool[idx + 1], st) == hipSuccess) ev_pending.push_back({kind, idx});
+  }
+  hipError_t ev_harvest() {
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return e;
+    for (auto& p : ev_pending) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, ev_pool[p.second], ev_pool[p.second + 1]);
+      if (e != hipSuccess) return e;
+      kt_ms[p.first] += ms;
+      kt_n[p.first] += 1;
+    }
+    ev_pending.clear();
+    ev_used = 0;
+    return hipSuccess;
+  }
+
+  ~npfem_batch_s() {
+    if (graph) hipGraphExecDestroy(graph);
+    for (hipEvent_t e : ev_pool) hipEventDestroy(e);
+    for (auto& c : cls) {
+      for (void* p : c.dev) hipFree(p);
+      if (c.op) hipFree(c.op);
+    }
+    for (void* p : allocs) hipFree(p);
+    if (cap_stream) hipStreamDestroy(cap_stream);
+  }
+};
+
+namespace {
+
+int dalloc(npfem_batch_s* b, void** p, size_t bytes, const char* what) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return hip_fail(e, what);
+  b->allocs.push_back(*p);
+  return NPFEM_OK;
+}
+
+template <typename T>
+int upload_vec(ClassState& c, const std::vector<T>& h, void** out, const char* what) {
+  void* p = nullptr;
+  const size_t bytes = std::max<size_t>(16, h.size() * sizeof(T));
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return hip_fail(e, what);
+  c.dev.push_back(p);
+  if (!h.empty()) {
+    e = hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, what);
+  }
+  *out = p;
+  return NPFEM_OK;
+}
+
+template <typename T>
+std::vector<T> cast_vec(const std::vector<double>& v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+// Uploads the class operators in the working precision T.
+template <typename T>
+int upload_class(ClassState& c) {
+  const MeshOps& M = c.ops;
+  std::vector<int> tri_v(4 * (size_t)M.F), hin_v(4 * (size_t)M.E);
+  std::vector<T> tri_rec(8 * (size_t)M.F, T(0)), hin_rec(8 * (size_t)M.E, T(0));
+  for (int t = 0; t < M.F; ++t) {
+    for (int r = 0; r < 3; ++r) tri_v[4 * (size_t)t + r] = M.tris[3 * (size_t)t + r];
+    tri_v[4 * (size_t)t + 3] = 0;
+    for (int k = 0; k < 6; ++k) tri_rec[8 * (size_t)t + k] = T(M.G[6 * (size_t)t + k]);
+    tri_rec[8 * (size_t)t + 6] = T(M.area[t]);
+  }
+  for (int e = 0; e < M.E; ++e) {
+    for (int r = 0; r < 4; ++r) {
+      hin_v[4 * (size_t)e + r] = M.hin[4 * (size_t)e + r];
+      hin_rec[8 * (size_t)e + r] = T(M.K[4 * (size_t)e + r]);
+    }
+    hin_rec[8 * (size_t)e + 4] = T(M.cw[e]);
+    hin_rec[8 * (size_t)e + 5] = T(M.rr[e]);
+  }
+  int rc;
+  void** v = c.view_ptrs;
+  if ((rc = upload_vec(c, tri_v, &v[0], "tri_v"))) return rc;
+  if ((rc = upload_vec(c, tri_rec, &v[1], "tri_rec"))) return rc;
+  if ((rc = upload_vec(c, hin_v, &v[2], "hin_v"))) return rc;
+  if ((rc = upload_vec(c, hin_rec, &v[3], "hin_rec"))) return rc;
+  if ((rc = upload_vec(c, M.vt_ptr, &v[4], "vt_ptr"))) return rc;
+  if ((rc = upload_vec(c, M.vt_tri, &v[5], "vt_tri"))) return rc;
+  if ((rc = upload_vec(c, cast_vec<T>(M.vt_g), &v[6], "vt_g"))) return rc;
+  if ((rc = upload_vec(c, M.vt_fan, &v[7], "vt_fan"))) return rc;
+  if ((rc = upload_vec(c, M.vh_ptr, &v[8], "vh_ptr"))) return rc;
+  if ((rc = upload_vec(c, M.vh_hin, &v[9], "vh_hin"))) return rc;
+  if ((rc = upload_vec(c, cast_vec<T>(M.vh_k), &v[10], "vh_k"))) return rc;
+  if ((rc = upload_vec(c, M.lap_ptr, &v[11], "lap_ptr"))) return rc;
+  if ((rc = upload_vec(c, M.lap_col, &v[12], "lap_col"))) return rc;
+  if ((rc = upload_vec(c, cast_vec<T>(M.lap_t), &v[13], "lap_t"))) return rc;
+  if ((rc = upload_vec(c, cast_vec<T>(M.lap_b), &v[14], "lap_b"))) return rc;
+  return NPFEM_OK;
+}
+
+template <typename T>
+ClassSlice<T> slice_of(const ClassState& c) {
+  ClassSlice<T> s;
+  ClassView<T>& v = s.cv;
+  v.N = c.N;
+  v.Npad = c.Npad;
+  v.F = c.F;
+  v.E = c.E;
+  v.tri_v = (const int4*)c.view_ptrs[0];
+  v.tri_rec = (const T*)c.view_ptrs[1];
+  v.hin_v = (const int4*)c.view_ptrs[2];
+  v.hin_rec = (const T*)c.view_ptrs[3];
+  v.vt_ptr = (const int*)c.view_ptrs[4];
+  v.vt_tri = (const int*)c.view_ptrs[5];
+  v.vt_g = (const T*)c.view_ptrs[6];
+  v.vt_fan = (const int*)c.view_ptrs[7];
+  v.vh_ptr = (const int*)c.view_ptrs[8];
+  v.vh_hin = (const int*)c.view_ptrs[9];
+  v.vh_k = (const T*)c.view_ptrs[10];
+  v.lap_ptr = (const int*)c.view_ptrs[11];
+  v.lap_col = (const int*)c.view_ptrs[12];
+  v.lap_t = (const T*)c.view_ptrs[13];
+  v.lap_b = (const T*)c.view_ptrs[14];
+  v.vol_rest = c.ops.vol_rest;
+  s.n_cells = c.n_cells;
+  s.cell0 = c.cell0;
+  s.col0 = c.col0;
+  s.elem0 = c.elem0;
+  s.vert0 = c.vert0;
+  s.mass = T(c.mat.vertex_mass);
+  s.w_nom[0] = T(c.mat.w_stretch);
+  s.w_nom[1] = T(c.mat.w_area);
+  s.w_nom[2] = T(c.mat.w_bend);
+  s.w_nom[3] = T(c.mat.w_volume);
+  return s;
+}
+
+int precision_of_gemm(int prec) {
+  switch (prec) {
+    case NPFEM_FP64: return 1;
+    case NPFEM_FP32: return 0;
+    case NPFEM_BF16_REFINE: return 2;
+    case NPFEM_FP16_REFINE: return 3;
+  }
+  return -1;
+}
+
+// Number of correction sweeps after each global solve. Per-cell weights make
+// the cell matrix A_c differ from the shared nominal A_0; the sweep
+// delta <- delta + A_0^-1 (r - A_c delta) contracts the error by at most
+// rho = max_c |A_c - A_0| / lambda_min(A_0), with lambda_min(A_0) >= m/h^2 + w_v
+// (both Laplacians are positive semi-definite). Low-precision operators add
+// two sweeps.
+int choose_refine(npfem_batch_s* b, double dt, int* out) {
+  if (b->n_refine_opt >= 0) {
+    *out = b->n_refine_opt;
+    return NPFEM_OK;
+  }
+  int n = (b->gemm_kind >= 2) ? 2 : 0;
+  if (b->per_cell) {
+    double rho = 0.0;
+    for (const ClassState& c : b->cls) {
+      const double w0[4] = {c.mat.w_stretch, c.mat.w_area, c.mat.w_bend, c.mat.w_volume};
+      const double lmin = c.mat.vertex_mass / (dt * dt) + c.mat.w_volume;
+      for (int i = 0; i < c.n_cells; ++i) {
+        const double* w = &b->weights_host[4 * (size_t)(c.cell0 + i)];
+        const double dev = std::fabs(w[0] + w[1] - w0[0] - w0[1]) * c.ops.norm_t +
+                           std::fabs(w[2] - w0[2]) * c.ops.norm_b + std::fabs(w[3] - w0[3]);
+        rho = std::max(rho, dev / lmin);
+      }
+    }
+    if (rho >= 0.9)
+      return fail(NPFEM_ERR_INVALID_ARG,
+                  "per-cell weights too far from the class material for the shared operator "
+                  "(contraction estimate %.3g); set n_refine explicitly or split the class", rho);
+    if (rho > 0.0) {
+      const double tol = b->fp64 ? 1e-15 : 1e-9;
+      const int need = (int)std::ceil(std::log(tol) / std::log(rho));
+      n = std::max(n, std::min(need, 60));
+    }
+  }
+  *out = n;
+  return NPFEM_OK;
+}
+
+int factorise(npfem_batch_s* b, double dt) {
+  int Nmax = 0;
+  for (auto& c : b->cls) Nmax = std::max(Nmax, c.Npad);
+  double* dA = nullptr;
+  double* scratch = nullptr;
+  int* dfail = nullptr;
+  double* dbeta = nullptr;
+  auto cleanup = [&]() {
+    if (dA) hipFree(dA);
+    if (scratch) hipFree(scratch);
+    if (dfail) hipFree(dfail);
+    if (dbeta) hipFree(dbeta);
+  };
+  hipError_t e = hipMalloc(&dA, sizeof(double) * (size_t)Nmax * Nmax);
+  if (e == hipSuccess) e = hipMalloc(&scratch, sizeof(double) * 2 * (size_t)Nmax);
+  if (e == hipSuccess) e = hipMalloc(&dfail, sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&dbeta, sizeof(double));
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "factorisation workspace");
+  }
+  std::vector<double> hA;
+  const size_t esz = b->gemm_kind == 1 ? 8 : (b->gemm_kind == 0 ? 4 : 2);
+  for (auto& c : b->cls) {
+    if (c.n_cells == 0) continue;
+    hA.assign((size_t)c.Npad * c.Npad, 0.0);
+    const double w0[4] = {c.mat.w_stretch, c.mat.w_area, c.mat.w_bend, c.mat.w_volume};
+    dense_system_matrix(c.ops, w0, c.mat.vertex_mass, dt, hA.data(), c.Npad);
+    int hfail = 0;
+    e = hipMemcpy(dA, hA.data(), sizeof(double) * hA.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(dfail, 0, sizeof(int));
+    if (e == hipSuccess) e = launch_spd_inverse(dA, c.N, c.Npad, scratch, dfail, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(&hfail, dfail, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      cleanup();
+      return hip_fail(e, "FP64 inverse");
+    }
+    if (hfail) {
+      cleanup();
+      return fail(NPFEM_ERR_NOT_SPD, "system matrix of a %d-vertex class is not SPD", c.N);
+    }
+    const double hm = dt * dt / c.mat.vertex_mass;
+    c.beta = 0.0;
+    if (b->gemm_kind >= 2) {
+      e = launch_max_abs_split(dA, c.N, c.Npad, hm, dbeta, nullptr);
+      if (e == hipSuccess) e = hipMemcpy(&c.beta, dbeta, sizeof(double), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "operator scale");
+      }
+    }
+    if (!c.op) {
+      e = hipMalloc(&c.op, esz * (size_t)c.Npad * c.Npad);
+      if (e != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "operator storage");
+      }
+    }
+    e = launch_convert_operator(b->gemm_kind, dA, c.Npad, hm, c.beta, c.op, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      cleanup();
+      return hip_fail(e, "operator conversion");
+    }
+  }
+  cleanup();
+  int rc = choose_refine(b, dt, &b->n_refine);
+  if (rc) return rc;
+  b->dt = dt;
+  return NPFEM_OK;
+}
+
+template <typename T>
+int enqueue_step(npfem_batch_s* b, const T* forces, double h, int n_iter, hipStream_t st) {
+  T* pos = static_cast<T*>(b->pos);
+  T* vel = static_cast<T*>(b->vel);
+  T* delta = static_cast<T*>(b->delta);
+  T* cterm = static_cast<T*>(b->cterm);
+  T* rhs = static_cast<T*>(b->rhs);
+  T* res = static_cast<T*>(b->res);
+  const T* w = b->per_cell ? static_cast<const T*>(b->weights_dev) : nullptr;
+  const bool lp = b->gemm_kind >= 2;
+  float* colmax = (b->gemm_kind == 3) ? b->colmax : nullptr;
+  const bool want_energy = (b->flags & NPFEM_OPT_ENERGY) != 0;
+  const bool timing = (b->flags & NPFEM_OPT_KERNEL_TIMING) != 0;
+#define NPFEM_TIMED(kind, expr, what)                   \
+  do {                                                  \
+    const int idx_ = timing ? b->ev_begin(st) : -1;     \
+    HIP_TRY(expr, what);                                \
+    if (idx_ >= 0) b->ev_end(idx_, kind, st);           \
+  } while (0)
+  if (timing && b->ev_used > 60000) HIP_TRY(b->ev_harvest(), "kernel timing");
+  for (auto& c : b->cls) {
+    if (c.n_cells == 0) continue;
+    NPFEM_TIMED(NPFEM_KERNEL_PREDICT,
+                launch_predict<T>(slice_of<T>(c), pos, vel, forces, b->sumN, delta, cterm,
+                                  b->status, h, st),
+                "predict");
+  }
+  for (int it = 0; it < n_iter; ++it) {
+    for (auto& c : b->cls) {
+      if (c.n_cells == 0) continue;
+      LocalArgs<T> a;
+      a.cs = slice_of<T>(c);
+      a.pos = pos;
+      a.sumN = b->sumN;
+      a.delta = delta;
+      a.cterm = cterm;
+      a.rhs = rhs;
+      a.weights = w;
+      a.energy = want_energy ? b->energy + (size_t)it * b->n_cells : nullptr;
+      a.colmax = colmax;
+      a.status = b->status;
+      a.h = h;
+      a.m = c.mat.vertex_mass;
+      a.max_vol_iter = b->max_vol_iter;
+      a.vol_tol = b->fp64 ? 1e-14 : 1e-6;
+      NPFEM_TIMED(NPFEM_KERNEL_LOCAL, launch_local<T>(a, c.local_block, st), "local step");
+    }
+    for (auto& c : b->cls) {
+      if (c.n_cells == 0) continue;
+      GemmArgs g;
+      g.A = c.op;
+      g.B = rhs + c.elem0;
+      g.C = delta + c.elem0;
+      g.colscale = colmax ? colmax + c.col0 : nullptr;
+      g.Npad = c.Npad;
+      g.ncols = 3 * c.n_cells;
+      g.mode = lp ? EPI_SPLIT_SET : EPI_SET;
+      g.hm = h * h / c.mat.vertex_mass;
+      g.beta = c.beta;
+      NPFEM_TIMED(NPFEM_KERNEL_GLOBAL, launch_gemm(b->gemm_kind, c.gemm_tile, g, st),
+                  "global step");
+      for (int s = 0; s < b->n_refine; ++s) {
+        NPFEM_TIMED(NPFEM_KERNEL_RESIDUAL,
+                    launch_residual<T>(slice_of<T>(c), rhs, delta, res, w, colmax, h, st),
+                    "residual");
+        GemmArgs r = g;
+        r.B = res + c.elem0;
+        r.mode = lp ? EPI_SPLIT_ADD : EPI_ADD;
+        NPFEM_TIMED(NPFEM_KERNEL_GLOBAL, launch_gemm(b->gemm_kind, c.gemm_tile, r, st),
+                    "refinement");
+      }
+    }
+  }
+  for (auto& c : b->cls) {
+    if (c.n_cells == 0) continue;
+    NPFEM_TIMED(NPFEM_KERNEL_UPDATE,
+                launch_update<T>(slice_of<T>(c), pos, vel, b->sumN, delta, h, st), "update");
+  }
+#undef NPFEM_TIMED
+  return NPFEM_OK;
+}
+
+int enqueue_any(npfem_batch_s* b, const void* forces, double h, int n_iter, hipStream_t st) {
+  if (b->fp64) return enqueue_step<double>(b, static_cast<const double*>(forces), h, n_iter, st);
+  return enqueue_step<float>(b, static_cast<const float*>(forces), h, n_iter, st);
+}
+
+int prepare_kernels(npfem_batch_s* b) {
+  for (auto& c : b->cls) {
+    hipError_t e = b->fp64 ? local_prepare<double>(slice_of<double>(c).cv, c.local_block)
+                           : local_prepare<float>(slice_of<float>(c).cv, c.local_block);
+    if (e != hipSuccess) return hip_fail(e, "local step attributes");
+  }
+  return NPFEM_OK;
+}
+
+int capture_graph(npfem_batch_s* b, const void* forces, double h, int n_iter) {
+  if (b->graph) {
+    hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  int rc = prepare_kernels(b);
+  if (rc) return rc;
+  HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  rc = enqueue_any(b, forces, h, n_iter, b->cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+  if (rc) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "end capture");
+  e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    b->graph = nullptr;
+    return hip_fail(e, "graph instantiate");
+  }
+  b->graph_forces = forces;
+  b->graph_iters = n_iter;
+  return NPFEM_OK;
+}
+
+int default_local_block(int N) {
+  if (N <= 256) return 128;
+  if (N <= 1536) return 256;
+  return 512;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* npfem_last_error(void) { return g_err.c_str(); }
+
+int npfem_create_mesh(const double* rest_xyz, int32_t n_verts, const int32_t* tris,
+                      int32_t n_tris, const npfem_material* mat, npfem_mesh* out) {
+  g_err.clear();
+  if (!out) return fail(NPFEM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!rest_xyz || !tris || !mat) return fail(NPFEM_ERR_INVALID_ARG, "NULL mesh argument");
+  const double wv[5] = {mat->w_stretch, mat->w_area, mat->w_bend, mat->w_volume, mat->vertex_mass};
+  for (int i = 0; i < 5; ++i) {
+    if (!std::isfinite(wv[i]) || wv[i] < 0.0)
+      return fail(NPFEM_ERR_INVALID_ARG, "material entries must be finite and non-negative");
+  }
+  if (!(mat->vertex_mass > 0.0)) return fail(NPFEM_ERR_INVALID_ARG, "vertex_mass must be > 0");
+  std::unique_ptr<npfem_mesh_s> m(new (std::nothrow) npfem_mesh_s);
+  if (!m) return fail(NPFEM_ERR_OOM, "host allocation");
+  std::string err;
+  const int rc = build_mesh_ops(rest_xyz, n_verts, tris, n_tris, m->ops, err);
+  if (rc) return fail(rc, "%s", err.c_str());
+  m->mat = *mat;
+  *out = m.release();
+  return NPFEM_OK;
+}
+
+int npfem_mesh_info(npfem_mesh m, int32_t* n_verts, int32_t* n_tris, int32_t* n_hinges,
+                    double* rest_volume) {
+  if (!m || m->tag != kMeshTag) return fail(NPFEM_ERR_INVALID_ARG, "not a mesh handle");
+  if (n_verts) *n_verts = m->ops.N;
+  if (n_tris) *n_tris = m->ops.F;
+  if (n_hinges) *n_hinges = m->ops.E;
+  if (rest_volume) *rest_volume = m->ops.vol_rest;
+  return NPFEM_OK;
+}
+
+int npfem_mesh_system_matrix(npfem_mesh m, const double* weights4, double dt, double* A_out) {
+  if (!m || m->tag != kMeshTag) return fail(NPFEM_ERR_INVALID_ARG, "not a mesh handle");
+  if (!A_out) return fail(NPFEM_ERR_INVALID_ARG, "A_out is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(NPFEM_ERR_INVALID_ARG, "dt must be > 0");
+  const double w0[4] = {m->mat.w_stretch, m->mat.w_area, m->mat.w_bend, m->mat.w_volume};
+  dense_system_matrix(m->ops, weights4 ? weights4 : w0, m->mat.vertex_mass, dt, A_out, m->ops.N);
+  return NPFEM_OK;
+}
+
+int npfem_create_batch(const npfem_mesh* meshes, int32_t n_meshes, const int32_t* cell_mesh,
+                       int32_t n_cells, const double* cell_weights, void* pos, void* vel,
+                       const npfem_options* opt, npfem_batch* out) {
+  g_err.clear();
+  if (!out) return fail(NPFEM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!meshes || n_meshes < 1 || !cell_mesh || n_cells < 1)
+    return fail(NPFEM_ERR_INVALID_ARG, "need at least one mesh and one cell");
+  if (!pos || !vel) return fail(NPFEM_ERR_INVALID_ARG, "pos and vel must be device pointers");
+  for (int i = 0; i < n_meshes; ++i)
+    if (!meshes[i] || meshes[i]->tag != kMeshTag)
+      return fail(NPFEM_ERR_INVALID_ARG, "meshes[%d] is not a mesh handle", i);
+  for (int c = 0; c < n_cells; ++c) {
+    if (cell_mesh[c] < 0 || cell_mesh[c] >= n_meshes)
+      return fail(NPFEM_ERR_INVALID_ARG, "cell_mesh[%d] out of range", c);
+    if (c > 0 && cell_mesh[c] < cell_mesh[c - 1])
+      return fail(NPFEM_ERR_INVALID_ARG, "cell_mesh must be non-decreasing (class-major order)");
+  }
+  npfem_options o{};
+  o.precision = NPFEM_FP32;
+  o.n_refine = -1;
+  if (opt) o = *opt;
+  const int kind = precision_of_gemm(o.precision);
+  if (kind < 0) return fail(NPFEM_ERR_INVALID_ARG, "unknown precision %d", o.precision);
+  if (o.n_refine < -1 || o.n_refine > 100) return fail(NPFEM_ERR_INVALID_ARG, "n_refine out of range");
+  if (o.max_vol_iter < 0 || o.max_vol_iter > 200)
+    return fail(NPFEM_ERR_INVALID_ARG, "max_vol_iter out of range");
+  if (cell_weights) {
+    for (long long i = 0; i < 4LL * n_cells; ++i)
+      if (!std::isfinite(cell_weights[i]) || cell_weights[i] < 0.0)
+        return fail(NPFEM_ERR_INVALID_ARG, "cell_weights must be finite and non-negative");
+  }
+
+  std::unique_ptr<npfem_batch_s> b(new (std::nothrow) npfem_batch_s);
+  if (!b) return fail(NPFEM_ERR_OOM, "host allocation");
+  HIP_TRY(hipGetDevice(&b->device), "hipGetDevice");
+  b->precision = o.precision;
+  b->gemm_kind = kind;
+  b->fp64 = (o.precision == NPFEM_FP64);
+  b->stream = static_cast<hipStream_t>(o.stream);
+  b->flags = o.flags;
+  b->n_refine_opt = o.n_refine;
+  b->max_vol_iter = o.max_vol_iter > 0 ? o.max_vol_iter : (b->fp64 ? 12 : 6);
+  b->n_cells = n_cells;
+  b->pos = pos;
+  b->vel = vel;
+  HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "capture stream");
+
+  const size_t tsz = b->fp64 ? sizeof(double) : sizeof(float);
+  // classes in mesh order; cells are class-major
+  b->cls.resize(n_meshes);
+  long long col = 0, elem = 0, vert = 0;
+  int c0 = 0;
+  for (int k = 0; k < n_meshes; ++k) {
+    ClassState& c = b->cls[k];
+    c.ops = meshes[k]->ops;
+    c.mat = meshes[k]->mat;
+    c.N = c.ops.N;
+    c.Npad = (c.N + 15) / 16 * 16;
+    c.F = c.ops.F;
+    c.E = c.ops.E;
+    int n = 0;
+    while (c0 + n < n_cells && cell_mesh[c0 + n] == k) ++n;
+    c.n_cells = n;
+    c.cell0 = c0;
+    c.col0 = col;
+    c.elem0 = elem;
+    c.vert0 = vert;
+    c.local_block = default_local_block(c.N);
+    c.gemm_tile = (3LL * n >= 1024) ? 3 : 0;
+    col += 3LL * n;
+    elem += 3LL * n * c.Npad;
+    vert += (long long)n * c.N;
+    c0 += n;
+    int rc = b->fp64 ? upload_class<double>(c) : upload_class<float>(c);
+    if (rc) return rc;
+  }
+  b->sumN = vert;
+  b->total_cols = col;
+  b->total_elems = elem;
+
+  // per-cell weights (kept on the device only when they differ from nominal)
+  b->weights_host.resize(4 * (size_t)n_cells);
+  for (int c = 0; c < n_cells; ++c) {
+    const npfem_material& m = b->cls[cell_mesh[c]].mat;
+    const double nom[4] = {m.w_stretch, m.w_area, m.w_bend, m.w_volume};
+    for (int i = 0; i < 4; ++i) {
+      const double w = cell_weights ? cell_weights[4 * (size_t)c + i] : nom[i];
+      b->weights_host[4 * (size_t)c + i] = w;
+      if (w != nom[i]) b->per_cell = true;
+    }
+  }
+  int rc;
+  if (b->per_cell) {
+    if ((rc = dalloc(b.get(), &b->weights_dev, tsz * 4 * (size_t)n_cells, "weights"))) return rc;
+    hipError_t e;
+    if (b->fp64) {
+      e = hipMemcpy(b->weights_dev, b->weights_host.data(), 8 * 4 * (size_t)n_cells,
+                    hipMemcpyHostToDevice);
+    } else {
+      std::vector<float> wf(b->weights_host.begin(), b->weights_host.end());
+      e = hipMemcpy(b->weights_dev, wf.data(), 4 * 4 * (size_t)n_cells, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return hip_fail(e, "weights upload");
+  }
+  const size_t colbytes = tsz * (size_t)b->total_elems;
+  if ((rc = dalloc(b.get(), &b->delta, colbytes, "delta"))) return rc;
+  if ((rc = dalloc(b.get(), &b->cterm, colbytes, "cterm"))) return rc;
+  if ((rc = dalloc(b.get(), &b->rhs, colbytes, "rhs"))) return rc;
+  if ((rc = dalloc(b.get(), &b->res, colbytes, "res"))) return rc;
+  void* p;
+  if ((rc = dalloc(b.get(), &p, sizeof(float) * (size_t)b->total_cols, "colmax"))) return rc;
+  b->colmax = static_cast<float*>(p);
+  if ((rc = dalloc(b.get(), &p, 64, "status"))) return rc;
+  b->status = static_cast<int*>(p);
+  if ((rc = dalloc(b.get(), &p, sizeof(double) * (size_t)n_cells, "volume"))) return rc;
+  b->volume_buf = static_cast<double*>(p);
+  HIP_TRY(hipMemset(b->delta, 0, colbytes), "memset");
+  HIP_TRY(hipMemset(b->rhs, 0, colbytes), "memset");
+  HIP_TRY(hipMemset(b->res, 0, colbytes), "memset");
+  HIP_TRY(hipMemset(b->cterm, 0, colbytes), "memset");
+  HIP_TRY(hipMemset(b->status, 0, 64), "memset");
+  HIP_TRY(hipDeviceSynchronize(), "create_batch");
+  *out = b.release();
+  return NPFEM_OK;
+}
+
+int npfem_step(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter) {
+  g_err.clear();
+  if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
+  if (!ext_forces) return fail(NPFEM_ERR_INVALID_ARG, "ext_forces is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(NPFEM_ERR_INVALID_ARG, "dt must be finite and > 0");
+  if (n_iter < 1 || n_iter > 1000) return fail(NPFEM_ERR_INVALID_ARG, "n_iter must be in [1, 1000]");
+  DeviceGuard guard(b->device);
+  int rc;
+  if (dt != b->dt) {
+    HIP_TRY(hipStreamSynchronize(b->stream), "sync before refactorisation");
+    if ((rc = factorise(b, dt))) return rc;
+    if (b->graph) {
+      hipGraphExecDestroy(b->graph);
+      b->graph = nullptr;
+    }
+  }
+  if ((b->flags & NPFEM_OPT_ENERGY) && n_iter > b->energy_cap) {
+    HIP_TRY(hipStreamSynchronize(b->stream), "sync before energy buffer");
+    void* p = nullptr;
+    HIP_TRY(hipMalloc(&p, sizeof(double) * (size_t)n_iter * b->n_cells), "energy buffer");
+    if (b->energy) {
+      auto it = std::find(b->allocs.begin(), b->allocs.end(), (void*)b->energy);
+      if (it != b->allocs.end()) b->allocs.erase(it);
+      hipFree(b->energy);
+    }
+    b->allocs.push_back(p);
+    b->energy = static_cast<double*>(p);
+    b->energy_cap = n_iter;
+    if (b->graph) {
+      hipGraphExecDestroy(b->graph);
+      b->graph = nullptr;
+    }
+  }
+  if (b->flags & (NPFEM_OPT_NO_GRAPH | NPFEM_OPT_KERNEL_TIMING)) {
+    if ((rc = prepare_kernels(b))) return rc;
+    if ((rc = enqueue_any(b, ext_forces, dt, n_iter, b->stream))) return rc;
+  } else {
+    if (!b->graph || b->graph_forces != ext_forces || b->graph_iters != n_iter) {
+      if ((rc = capture_graph(b, ext_forces, dt, n_iter))) return rc;
+    }
+    HIP_TRY(hipGraphLaunch(b->graph, b->stream), "graph launch");
+  }
+  b->energy_iters = n_iter;
+  if (b->flags & NPFEM_OPT_SYNC_CHECK) return npfem_sync_status(b);
+  return NPFEM_OK;
+}
+
+int npfem_sync_status(npfem_batch b) {
+  if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
+  DeviceGuard guard(b->device);
+  int st = 0;
+  HIP_TRY(hipStreamSynchronize(b->stream), "sync");
+  HIP_TRY(hipMemcpy(&st, b->status, sizeof(int), hipMemcpyDeviceToHost), "status read");
+  HIP_TRY(hipMemset(b->status, 0, sizeof(int)), "status clear");
+  HIP_TRY(hipDeviceSynchronize(), "status clear");
+  if (st & ST_NONFINITE) return fail(NPFEM_ERR_NONFINITE, "non-finite value in state, forces or a reduction");
+  return NPFEM_OK;
+}
+
+int npfem_get_energy(npfem_batch b, double* host_out, int32_t capacity, int32_t* n_iter_out) {
+  if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
+  if (!(b->flags & NPFEM_OPT_ENERGY) || !b->energy)
+    return fail(NPFEM_ERR_INVALID_ARG, "energy recording is off (NPFEM_OPT_ENERGY) or no step ran");
+  const long long need = (long long)b->energy_iters * b->n_cells;
+  if (!host_out || capacity < need) return fail(NPFEM_ERR_INVALID_ARG, "capacity below n_iter * n_cells");
+  DeviceGuard guard(b->device);
+  HIP_TRY(hipStreamSynchronize(b->stream), "sync");
+  HIP_TRY(hipMemcpy(host_out, b->energy, sizeof(double) * need, hipMemcpyDeviceToHost), "energy read");
+  if (n_iter_out) *n_iter_out = b->energy_iters;
+  return NPFEM_OK;
+}
+
+int npfem_get_volume(npfem_batch b, double* host_out) {
+  if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
+  if (!host_out) return fail(NPFEM_ERR_INVALID_ARG, "host_out is NULL");
+  DeviceGuard guard(b->device);
+  for (auto& c : b->cls) {
+    hipError_t e = b->fp64 ? launch_volume<double>(slice_of<double>(c), (const double*)b->pos,
+                                                   b->sumN, b->volume_buf, b->stream)
+                           : launch_volume<float>(slice_of<float>(c), (const float*)b->pos,
+                                                  b->sumN, b->volume_buf, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "volume");
+  }
+  HIP_TRY(hipStreamSynchronize(b->stream), "sync");
+  HIP_TRY(hipMemcpy(host_out, b->volume_buf, sizeof(double) * b->n_cells, hipMemcpyDeviceToHost),
+          "volume read");
+  return NPFEM_OK;
+}
+
+int npfem_kernel_times(npfem_batch b, double* ms_out, int64_t* launches_out, int32_t reset) {
+  if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
+  if (!(b->flags & NPFEM_OPT_KERNEL_TIMING))
+    return fail(NPFEM_ERR_INVALID_ARG, "kernel timing is off (NPFEM_OPT_KERNEL_TIMING)");
+  DeviceGuard guard(b->device);
+  HIP_TRY(b->ev_harvest(), "kernel timing");
+  for (int k = 0; k < NPFEM_KERNEL_KINDS; ++k) {
+    if (ms_out) ms_out[k] = b->kt_ms[k];
+    if (launches_out) launches_out[k] = b->kt_n[k];
+    if (reset) {
+      b->kt_ms[k] = 0.0;
+      b->kt_n[k] = 0;
+    }
+  }
+  return NPFEM_OK;
+}
+
+int npfem_free(void* handle) {
+  if (!handle) return NPFEM_OK;
+  const uint32_t tag = *static_cast<uint32_t*>(handle);
+  if (tag == kMeshTag) {
+    npfem_mesh_s* m = static_cast<npfem_mesh_s*>(handle);
+    m->tag = 0;
+    delete m;
+    return NPFEM_OK;
+  }
+  if (tag == kBatchTag) {
+    npfem_batch_s* b = static_cast<npfem_batch_s*>(handle);
+    DeviceGuard guard(b->device);
+    hipStreamSynchronize(b->stream);
+    b->tag = 0;
+    delete b;
+    return NPFEM_OK;
+  }
+  return fail(NPFEM_ERR_INVALID_ARG, "unknown handle");
+}
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+// Internal types shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace npfem {
+
+// Device-resident, read-only description of one mesh class. Element records
+// are padded to 16/32-byte multiples so that a thread fetches one record with
+// vector loads; incidence lists are CSR over vertices.
+template <typename T>
+struct ClassView {
+  int N;      // vertices
+  int Npad;   // rows of the padded column layout (multiple of 16)
+  int F;      // triangles
+  int E;      // hinges
+  const int4* tri_v;   // [F] (a, b, c, 0)
+  const T* tri_rec;    // [F][8]: G (3x2 row-major), area, 0
+  const int4* hin_v;   // [E] (i, j, k, l)
+  const T* hin_rec;    // [E][8]: K[4], c, r_rest, 0, 0
+  const int* vt_ptr;   // [N+1] vertex -> incident triangle entries
+  const int* vt_tri;   // triangle index of each entry (ascending per vertex)
+  const T* vt_g;       // [entries][2] G row of the vertex in that triangle
+  const int* vt_fan;   // other two vertices (b | c << 16), (v, b, c) counter-clockwise
+  const int* vh_ptr;   // [N+1] vertex -> incident hinge entries
+  const int* vh_hin;   // hinge index of each entry (ascending per vertex)
+  const T* vh_k;       // stencil coefficient of the vertex in that hinge
+  const int* lap_ptr;  // [N+1] CSR of the Laplacian pattern (diagonal included)
+  const int* lap_col;
+  const T* lap_t;      // sum_t A_t G_t G_t^T entries
+  const T* lap_b;      // sum_e c_e K_e K_e^T entries
+  double vol_rest;
+};
+
+// Per-class slice of the batch.
+template <typename T>
+struct ClassSlice {
+  ClassView<T> cv;
+  int n_cells;       // cells of this class
+  int cell0;         // global index of its first cell
+  long long col0;    // first column (3 per cell) of the class in the column buffers
+  long long elem0;   // element offset of that column (classes differ in Npad)
+  long long vert0;   // first vertex of its first cell in the SoA state
+  T mass;
+  T w_nom[4];        // nominal weights
+};
+
+// Kernel launch helpers (defined in the .hip files). All take the stream last.
+struct StepScalars {
+  double h;       // time step
+  double m;       // vertex mass of the class
+};
+
+template <typename T>
+struct LocalArgs {
+  ClassSlice<T> cs;
+  const T* pos;        // state SoA [3][sumN]
+  long long sumN;
+  const T* delta;      // column buffers [cols][Npad] (batch base; class at cs.elem0)
+  const T* cterm;      // inertial term (m/h) v + f, same layout
+  T* rhs;              // output r = b - A x, same layout
+  const T* weights;    // [n_cells_total][4] or nullptr
+  double* energy;      // [n_cells_total] slot for this iteration, or nullptr
+  float* colmax;       // [cols] max |r| per column (low-precision global step), or nullptr
+  int* status;         // device flags
+  double h, m;
+  int max_vol_iter;
+  double vol_tol;
+};
+
+enum EpilogueMode : int { EPI_SET = 0, EPI_ADD = 1, EPI_SPLIT_SET = 2, EPI_SPLIT_ADD = 3 };
+
+struct GemmArgs {
+  const void* A;       // [Npad][Npad] symmetric operator (element type per kernel)
+  const void* B;       // input columns [ncols][Npad] (float or double)
+  void* C;             // output columns [ncols][Npad]
+  const float* colscale;  // per-column scale of B for low-precision operands, or nullptr
+  int Npad;
+  int ncols;
+  int mode;            // EpilogueMode
+  double hm;           // h^2/m (split epilogue)
+  double beta;         // scale of the stored low-precision operator (split epilogue)
+};
+
+enum StatusBits : int { ST_NONFINITE = 1 };
+
+// ---- launchers ----
+template <typename T>
+hipError_t launch_predict(const ClassSlice<T>& cs, const T* pos, const T* vel, const T* force,
+                          long long sumN, T* delta, T* cterm, int* status, double h,
+                          hipStream_t st);
+template <typename T>
+hipError_t launch_update(const ClassSlice<T>& cs, T* pos, T* vel, long long sumN, const T* delta,
+                         double h, hipStream_t st);
+template <typename T>
+hipError_t launch_local(const LocalArgs<T>& a, int block, hipStream_t st);
+template <typename T>
+size_t local_smem_bytes(const ClassView<T>& cv, int block);
+template <typename T>
+hipError_t local_prepare(const ClassView<T>& cv, int block);
+template <typename T>
+hipError_t launch_residual(const ClassSlice<T>& cs, const T* rhs, const T* delta, T* res,
+                           const T* weights, float* colmax, double h, hipStream_t st);
+template <typename T>
+hipError_t launch_volume(const ClassSlice<T>& cs, const T* pos, long long sumN, double* out,
+                         hipStream_t st);
+
+// Global-step GEMM variants. kind: 0 = FP32, 1 = FP64, 2 = BF16, 3 = FP16.
+hipError_t launch_gemm(int kind, int tile, const GemmArgs& g, hipStream_t st);
+int gemm_num_tiles(int kind);
+
+// FP64 Gauss-Jordan inverse of an SPD matrix in place (device, n x n,
+// leading dimension ld); *pivot_fail set non-zero if a pivot is <= 0.
+hipError_t launch_spd_inverse(double* A, int n, int ld, double* scratch, int* pivot_fail,
+                              hipStream_t st);
+// Convert an FP64 padded inverse to the stored operator.
+hipError_t launch_convert_operator(int kind, const double* Ainv, int Npad, double hm, double beta,
+                                   void* out, hipStream_t st);
+hipError_t launch_max_abs_split(const double* Ainv, int n, int Npad, double hm, double* out,
+                                hipStream_t st);
+
+}  // namespace npfem

@@ -1,0 +1,188 @@
+"""Python objects over the C ABI: meshes, batches and time stepping.
+
+PyTorch provides device memory and the stream; every step of the solver runs
+in the HIP library (libnpfem.so). There is no fallback path: if the library or
+a GPU is missing, construction raises.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_PREC = {"fp64": _lib.FP64, "fp32": _lib.FP32, "bf16": _lib.BF16_REFINE, "fp16": _lib.FP16_REFINE}
+
+
+def precision_code(p) -> int:
+    if isinstance(p, int):
+        return p
+    return _PREC[p]
+
+
+def state_dtype(precision) -> torch.dtype:
+    return torch.float64 if precision_code(precision) == _lib.FP64 else torch.float32
+
+
+class Mesh:
+    """One mesh class: rest shape, triangles and nominal material (host only)."""
+
+    def __init__(self, rest_xyz, tris, weights=(1.0, 1.0, 0.01, 10.0), vertex_mass=1e-3):
+        lib = _lib.load()
+        x = np.ascontiguousarray(rest_xyz, dtype=np.float64)
+        t = np.ascontiguousarray(tris, dtype=np.int32)
+        if x.ndim != 2 or x.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 3:
+            raise ValueError("rest_xyz must be [N, 3] and tris [F, 3]")
+        mat = _lib.Material(*(float(w) for w in weights), float(vertex_mass))
+        h = ctypes.c_void_p()
+        _lib.check(lib.npfem_create_mesh(x.ctypes.data, x.shape[0], t.ctypes.data, t.shape[0],
+                                         ctypes.byref(mat), ctypes.byref(h)))
+        self.handle = h
+        self.weights = tuple(float(w) for w in weights)
+        self.vertex_mass = float(vertex_mass)
+        self.n_verts = int(x.shape[0])
+
+    def info(self):
+        n, f, e = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        v = ctypes.c_double()
+        _lib.check(_lib.load().npfem_mesh_info(self.handle, ctypes.byref(n), ctypes.byref(f),
+                                               ctypes.byref(e), ctypes.byref(v)))
+        return n.value, f.value, e.value, v.value
+
+    def system_matrix(self, dt, weights=None) -> np.ndarray:
+        A = np.empty((self.n_verts, self.n_verts), dtype=np.float64)
+        w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+        _lib.check(_lib.load().npfem_mesh_system_matrix(
+            self.handle, None if w is None else w.ctypes.data, float(dt), A.ctypes.data))
+        return A
+
+    def close(self):
+        if self.handle:
+            _lib.load().npfem_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Cells of several mesh classes stepped together on one GPU.
+
+    pos, vel: CUDA tensors [3, sum_N] (float64 for precision 'fp64', else
+    float32), cell-local coordinates, updated in place by step().
+    """
+
+    def __init__(self, meshes, cell_mesh, pos: torch.Tensor, vel: torch.Tensor, cell_weights=None,
+                 precision="fp32", n_refine=-1, max_vol_iter=0, energy=False, graph=True,
+                 sync_check=False, kernel_timing=False, stream=None):
+        lib = _lib.load()
+        code = precision_code(precision)
+        dt_ = state_dtype(code)
+        for name, t in (("pos", pos), ("vel", vel)):
+            if not (t.is_cuda and t.dtype == dt_ and t.is_contiguous() and t.dim() == 2
+                    and t.shape[0] == 3):
+                raise ValueError(f"{name} must be a contiguous CUDA {dt_} tensor [3, sum_N]")
+        self.pos, self.vel = pos, vel
+        self.meshes = list(meshes)
+        cm = np.ascontiguousarray(cell_mesh, dtype=np.int32)
+        self.n_cells = int(cm.shape[0])
+        sum_n = int(sum(self.meshes[k].n_verts for k in cm))
+        if pos.shape[1] != sum_n or vel.shape[1] != sum_n:
+            raise ValueError(f"state has {pos.shape[1]} vertices, cells need {sum_n}")
+        w = None if cell_weights is None else np.ascontiguousarray(cell_weights, dtype=np.float64)
+        if w is not None and w.shape != (self.n_cells, 4):
+            raise ValueError("cell_weights must be [n_cells, 4]")
+        flags = 0
+        if energy:
+            flags |= _lib.OPT_ENERGY
+        if not graph:
+            flags |= _lib.OPT_NO_GRAPH
+        if sync_check:
+            flags |= _lib.OPT_SYNC_CHECK
+        if kernel_timing:
+            flags |= _lib.OPT_KERNEL_TIMING
+        if stream is None:
+            stream = torch.cuda.current_stream(pos.device)
+        self.stream = stream
+        opt = _lib.Options(code, int(n_refine), int(max_vol_iter), flags,
+                           ctypes.c_void_p(stream.cuda_stream))
+        handles = (ctypes.c_void_p * len(self.meshes))(*[m.handle.value for m in self.meshes])
+        h = ctypes.c_void_p()
+        with torch.cuda.device(pos.device):
+            _lib.check(lib.npfem_create_batch(
+                handles, len(self.meshes), cm.ctypes.data, self.n_cells,
+                None if w is None else w.ctypes.data, pos.data_ptr(), vel.data_ptr(),
+                ctypes.byref(opt), ctypes.byref(h)))
+        self.handle = h
+        self.precision = code
+        self.dtype = dt_
+        self._forces = None
+
+    def step(self, forces: torch.Tensor, dt: float, n_iter: int):
+        if not (forces.is_cuda and forces.dtype == self.dtype and forces.is_contiguous()
+                and tuple(forces.shape) == tuple(self.pos.shape)):
+            raise ValueError("forces must match pos (contiguous CUDA, same dtype and shape)")
+        self._forces = forces  # keep alive while the graph may reference it
+        _lib.check(_lib.load().npfem_step(self.handle, forces.data_ptr(), float(dt), int(n_iter)))
+
+    def sync_status(self):
+        _lib.check(_lib.load().npfem_sync_status(self.handle))
+
+    def energy(self) -> np.ndarray:
+        n_it = ctypes.c_int32()
+        cap = 1000 * self.n_cells
+        buf = np.empty(cap, dtype=np.float64)
+        _lib.check(_lib.load().npfem_get_energy(self.handle, buf.ctypes.data, cap,
+                                                ctypes.byref(n_it)))
+        return buf[: n_it.value * self.n_cells].reshape(n_it.value, self.n_cells).copy()
+
+    def volume(self) -> np.ndarray:
+        out = np.empty(self.n_cells, dtype=np.float64)
+        _lib.check(_lib.load().npfem_get_volume(self.handle, out.ctypes.data))
+        return out
+
+    def kernel_times(self, reset=False):
+        """{kind: (total ms, launches)} accumulated from per-kernel HIP events."""
+        ms = np.zeros(len(_lib.KERNEL_KINDS), dtype=np.float64)
+        n = np.zeros(len(_lib.KERNEL_KINDS), dtype=np.int64)
+        _lib.check(_lib.load().npfem_kernel_times(self.handle, ms.ctypes.data, n.ctypes.data,
+                                                  1 if reset else 0))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(_lib.KERNEL_KINDS)}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.load().npfem_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def meshes_for(susp):
+    """Mesh objects for the classes of a workload suspension."""
+    return [Mesh(c.rest, c.tris, c.weights, c.mass) for c in susp.classes]
+
+
+def batch_from_suspension(susp, precision="fp32", device="cuda", per_cell_weights=None, **kw):
+    """Uploads a workload suspension; returns (batch, pos, vel, forces, meshes).
+
+    per_cell_weights: None = pass the suspension's weights only when they differ
+    from each class's nominal material."""
+    dt_ = state_dtype(precision)
+    pos = torch.tensor(susp.x0, dtype=dt_, device=device).contiguous()
+    vel = torch.tensor(susp.v0, dtype=dt_, device=device).contiguous()
+    f = torch.tensor(susp.forces, dtype=dt_, device=device).contiguous()
+    meshes = meshes_for(susp)
+    if per_cell_weights is None:
+        per_cell_weights = not susp.uniform_weights()
+    w = susp.weights if per_cell_weights else None
+    b = Batch(meshes, susp.cell_class, pos, vel, cell_weights=w, precision=precision, **kw)
+    return b, pos, vel, f, meshes

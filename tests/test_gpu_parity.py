@@ -1,0 +1,182 @@
+"""GPU path (through the C ABI) against the FP64 oracle, element by element.
+
+Error metric: max over checked cells of max_v |x - x_ref| / R_cell with
+R_cell = max_v |x_ref_v - centroid|. Bounds: FP64 1e-12, FP32 1e-6,
+BF16/FP16 global step with refinement 1e-5. Cells are independent, so a
+sampled cell of a large batch is checked exactly against a one-cell oracle run.
+"""
+import numpy as np
+import pytest
+
+from npfem_workload import suspensions as W
+from oracle import solver as S
+
+from gpu_helpers import as_precision, cell_error, log, max_error, oracle_cells, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16": 1e-5, "fp16": 1e-5}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2011_04332_amd import _lib
+    _lib.load()  # fails loudly if the HIP library is missing
+
+
+def test_single_rbc_fp64_full_run():
+    """1 RBC (162 vertices), FP64, 100 steps x 20 PD iterations, dt 1e-4."""
+    s = W.single_rbc()
+    log("single_rbc fp64 100x20")
+    x, v = run_gpu(s, "fp64")
+    ref = oracle_cells(s, [0])
+    err = max_error(s, x, ref)
+    log(f"single_rbc fp64 err {err:.3e}")
+    assert err <= TOL["fp64"]
+    assert np.abs(v.T - ref[0][1]).max() <= 1e-8 * max(1.0, np.abs(ref[0][1]).max())
+
+
+def test_single_rbc_fp64_stiff():
+    s = W.stiff(W.single_rbc(n_steps=10))
+    log("single_rbc fp64 stiff dt 1e-2")
+    x, _ = run_gpu(s, "fp64")
+    err = max_error(s, x, oracle_cells(s, [0]))
+    log(f"stiff fp64 err {err:.3e}")
+    assert err <= TOL["fp64"]
+
+
+@pytest.mark.parametrize("stiff", [False, True])
+def test_rbc_lattice_fp32_sample(stiff):
+    """64 RBCs (642 vertices): 192 columns span a ragged tile; 4 cells checked."""
+    s = W.rbc_lattice(n_cells=64, n_steps=6 if stiff else 10)
+    if stiff:
+        s = W.stiff(s)
+    s = as_precision(s, np.float32)
+    log(f"rbc_lattice fp32 64 cells stiff={stiff}")
+    x, _ = run_gpu(s, "fp32")
+    cells = [0, 17, 42, 63]
+    err = max_error(s, x, oracle_cells(s, cells))
+    log(f"rbc_lattice fp32 stiff={stiff} err {err:.3e}")
+    assert err <= TOL["fp32"]
+
+
+def test_rbc_lattice_full_size_sampled():
+    """The benchmark workload at full size (4096 RBCs), a few steps, 3 sampled cells."""
+    s = as_precision(W.rbc_lattice(n_steps=5), np.float32)
+    log("rbc_lattice fp32 4096 cells, 5 steps")
+    x, _ = run_gpu(s, "fp32")
+    cells = W.sample_cells(s, [3])
+    err = max_error(s, x, oracle_cells(s, cells))
+    log(f"rbc_lattice 4096 err {err:.3e}")
+    assert err <= TOL["fp32"]
+
+
+@pytest.mark.parametrize("stiff", [False, True])
+def test_uneven_batch_per_cell_weights(stiff):
+    """RBC + platelet + large-cell classes with per-cell weights (+-20 %)."""
+    s = W.uneven(n_rbc=20, n_plt=12, n_large=3, n_steps=3 if stiff else 4)
+    if stiff:
+        s = W.stiff(s)
+    s = as_precision(s, np.float32)
+    log(f"uneven fp32 stiff={stiff}")
+    x, _ = run_gpu(s, "fp32")
+    cells = [0, 19, 20, 31, 32, 34]
+    err = max_error(s, x, oracle_cells(s, cells))
+    log(f"uneven stiff={stiff} err {err:.3e}")
+    assert err <= TOL["fp32"]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_mixed_precision_refined(prec):
+    s = as_precision(W.precision_sweep(n_rbc=48, n_plt=16, n_steps=5), np.float32)
+    log(f"precision {prec}")
+    x, _ = run_gpu(s, prec)
+    cells = [0, 47, 48, 63]
+    err = max_error(s, x, oracle_cells(s, cells))
+    log(f"precision {prec} err {err:.3e}")
+    assert err <= TOL[prec]
+
+
+def test_momentum_and_rest_invariants():
+    import torch
+    from paper_2011_04332_amd import solver
+    s = as_precision(W.rbc_lattice(n_cells=16, n_steps=1), np.float32)
+    b, pos, vel, f, _ = solver.batch_from_suspension(s, "fp32")
+    v0 = vel.double().clone()
+    b.step(f, 1e-2, 5)
+    b.sync_status()
+    # sum m v_{n+1} = sum m v_n + h sum f, per cell
+    n = s.classes[0].n_verts
+    dv = (vel.double() - v0).reshape(3, 16, n).sum(-1)
+    df = 1e-2 / 1e-3 * f.double().reshape(3, 16, n).sum(-1)
+    assert torch.allclose(dv, df, rtol=0, atol=1e-4 * df.abs().max().item() + 1e-6)
+    b.close()
+    # rest state with no forces stays at rest
+    z = W.rbc_lattice(n_cells=8, n_steps=1)
+    z.forces[:] = 0.0
+    b, pos, vel, f, _ = solver.batch_from_suspension(as_precision(z, np.float32), "fp32")
+    x0 = pos.clone()
+    for _ in range(5):
+        b.step(f, 1e-4, 10)
+    b.sync_status()
+    R = 3.91
+    assert (pos - x0).abs().max().item() <= 1e-6 * R
+    b.close()
+
+
+def test_energy_monotone_stiff_fp64():
+    from paper_2011_04332_amd import solver
+    s = W.stiff(W.single_rbc(n_steps=1))
+    s.x0 = s.x0 + 0.05 * np.random.default_rng(0).standard_normal(s.x0.shape)
+    b, pos, vel, f, _ = solver.batch_from_suspension(s, "fp64", energy=True)
+    b.step(f, s.dt, 25)
+    E = b.energy()[:, 0]
+    b.close()
+    assert np.all(np.diff(E) <= 1e-12 * abs(E[0])) and E[-1] < E[0]
+    mc, x0, v0, fo, w = s.cell_arrays(0)
+    cs = S.CellSolver(S.operators_for(mc), S.Params(tuple(w), mc.mass, s.dt))
+    _, _, Eo = cs.step(x0, v0, fo, 25, record_energy=True)
+    assert np.allclose(E, Eo[:25], rtol=1e-10, atol=0)
+
+
+def test_bitwise_reproducible_and_graph_equals_eager():
+    s = as_precision(W.uneven(n_rbc=6, n_plt=4, n_large=1, n_steps=3), np.float32)
+    a, _ = run_gpu(s, "fp32")
+    b, _ = run_gpu(s, "fp32")
+    c, _ = run_gpu(s, "fp32", graph=False)
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_nonfinite_forces_are_reported():
+    import torch
+    from paper_2011_04332_amd import _lib, solver
+    s = W.rbc_lattice(n_cells=2, n_steps=1)
+    b, pos, vel, f, _ = solver.batch_from_suspension(s, "fp32")
+    f[0, 5] = float("nan")
+    b.step(f, 1e-4, 2)
+    with pytest.raises(_lib.NpfemError) as e:
+        b.sync_status()
+    assert e.value.code == _lib.ERR_NONFINITE
+    b.sync_status()  # flag cleared
+    b.close()
+
+
+def test_time_step_change_refactors():
+    s = as_precision(W.rbc_lattice(n_cells=4, n_steps=2), np.float32)
+    import torch
+    from paper_2011_04332_amd import solver
+    b, pos, vel, f, _ = solver.batch_from_suspension(s, "fp32")
+    b.step(f, 1e-4, 5)
+    b.step(f, 1e-2, 5)
+    b.sync_status()
+    x = pos.double().cpu().numpy()
+    b.close()
+    for c in (0, 3):
+        mc, x0, v0, fo, w = s.cell_arrays(c)
+        o = S.operators_for(mc)
+        xa, va, _ = S.CellSolver(o, S.Params(tuple(w), mc.mass, 1e-4)).step(x0, v0, fo, 5)
+        xb, _, _ = S.CellSolver(o, S.Params(tuple(w), mc.mass, 1e-2)).step(xa, va, fo, 5)
+        assert cell_error(s, x, c, xb) <= TOL["fp32"]
