@@ -60,7 +60,7 @@ def round_inputs(s, precision):
         return s
     r = lambda a: a.astype(np.float32).astype(np.float64)
     return Suspension(s.classes, s.cell_class, s.origins, r(s.x0), r(s.v0), r(s.forces),
-                      r(s.weights), s.dt, s.n_iter, s.n_steps, s.name, dict(s.extra))
+                      (s.weights if s.uniform_weights() else r(s.weights)), s.dt, s.n_iter, s.n_steps, s.name, dict(s.extra))
 
 
 def _oracle_cell(args):
@@ -114,7 +114,21 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (3 times), the "
+                         "reference for scaling FETCH_SIZE / WRITE_SIZE counters")
     a = ap.parse_args()
+    if a.calibrate_copy_mb:
+        import torch
+        n = a.calibrate_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 4, "copies": 3}), flush=True)
+        return
     if a.gpus != 1:
         print("bench.py: this build measures one GPU only (the per-cell step needs no "
               "exchange between GPUs); run with --gpus 1", file=sys.stderr)
@@ -130,11 +144,15 @@ def main():
     print(f"[bench] workload {a.workload}: {desc}; {a.precision}; steps {a.steps} warmup {a.warmup}",
           file=sys.stderr, flush=True)
 
-    b, pos, vel, f, meshes = solver.batch_from_suspension(s, precision=a.precision)
+    b, pos, vel, f, meshes = solver.batch_from_suspension(s, precision=a.precision,
+                                                          autotune=not a.no_autotune)
     x_init, v_init = pos.clone(), vel.clone()
-    for _ in range(a.warmup):
+    for _ in range(max(1, a.warmup)):
         b.step(f, dt, n_iter)
     b.sync_status()
+    configs = [b.config(k) for k in range(len(s.classes))]
+    print(f"[bench] launch configs per class (local block, tile m, tile n, sweeps): {configs}",
+          file=sys.stderr, flush=True)
     pos.copy_(x_init)
     vel.copy_(v_init)
     torch.cuda.synchronize()
@@ -159,6 +177,8 @@ def main():
         bt = solver.Batch(meshes, s.cell_class, pos, vel,
                           cell_weights=None if s.uniform_weights() else s.weights,
                           precision=a.precision, kernel_timing=True)
+        for k, cfg in enumerate(configs):
+            bt.set_config(k, cfg)
         for i in range(a.steps):
             bt.step(f, dt, n_iter)
             if i + 1 == cpu_steps:
@@ -220,6 +240,8 @@ def main():
         "dtype": DTYPE[a.precision],
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: {desc}", "cells": s.n_cells, "pd_iterations": n_iter,
+                   "launch": {s.classes[k].name: {"local_block": c[0], "gemm_tile": [c[1], c[2]],
+                                                  "sweeps": c[3]} for k, c in enumerate(configs)},
                    "dt": dt, "precision": a.precision},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -177,6 +177,18 @@ int npfem_get_energy(npfem_batch b, double* host_out, int32_t capacity, int32_t*
  * positions into host [n_cells]. */
 int npfem_get_volume(npfem_batch b, double* host_out);
 
+/* Launch configuration chosen for mesh class cls (after the first step, which
+ * runs the autotuner when NPFEM_OPT_AUTOTUNE is set): out[0] local-step
+ * workgroup size, out[1] / out[2] global-step GEMM tile rows / columns,
+ * out[3] correction sweeps per global solve. Host only. */
+int npfem_batch_config(npfem_batch b, int32_t cls, int32_t out[4]);
+
+/* Pins the launch configuration of class cls (same layout as
+ * npfem_batch_config; in[3] < 0 keeps the automatic sweep count), e.g. to
+ * replay a configuration tuned earlier. The next step re-captures its graph.
+ * Errors: INVALID_ARG for an unsupported workgroup size or tile shape. */
+int npfem_set_batch_config(npfem_batch b, int32_t cls, const int32_t in[4]);
+
 /* Requires NPFEM_OPT_KERNEL_TIMING. Synchronises, converts every event pair
  * recorded since the last call into elapsed milliseconds and adds them to
  * running totals per kernel kind; writes the totals (host [NPFEM_KERNEL_KINDS]

@@ -41,6 +41,8 @@ EXPORTED = [
     "npfem_sync_status",
     "npfem_get_energy",
     "npfem_get_volume",
+    "npfem_batch_config",
+    "npfem_set_batch_config",
     "npfem_kernel_times",
     "npfem_free",
     "npfem_last_error",
@@ -96,6 +98,8 @@ def load() -> ctypes.CDLL:
     lib.npfem_get_energy.argtypes = [P, P, I32, P]
     lib.npfem_get_volume.argtypes = [P, P]
     lib.npfem_kernel_times.argtypes = [P, P, P, I32]
+    lib.npfem_batch_config.argtypes = [P, I32, P]
+    lib.npfem_set_batch_config.argtypes = [P, I32, P]
     lib.npfem_free.argtypes = [P]
     lib.npfem_last_error.argtypes = []
     lib.npfem_last_error.restype = ctypes.c_char_p

@@ -34,6 +34,8 @@ struct Mfma4<float> {
   static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  // result register r of lane l holds row 4*(l/16) + r of column l%16
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 template <>
 struct Mfma4<double> {
@@ -41,11 +43,27 @@ struct Mfma4<double> {
   static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  // result register r of lane l holds row l/16 + 4*r of column l%16
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
 // Row pads chosen so that the 4 k-rows read by one MFMA operand fetch land
 // 16 banks apart.
 __host__ __device__ constexpr int lds_pad(int w) { return ((16 - w) % 64 + 64) % 64; }
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2). Remap the linear id so that every XCD receives a contiguous range of
+// tiles, row tiles fastest: the row tiles of one column strip then share an
+// L2 and read the strip from HBM once.
+__device__ __forceinline__ void xcd_tile(int& mt, int& nt) {
+  const int nbx = gridDim.x, total = gridDim.x * gridDim.y;
+  const int id = blockIdx.x + blockIdx.y * nbx;
+  const int xcd = id & 7, slot = id >> 3;
+  const int per = total >> 3, rem = total & 7;
+  const int logical = xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+  mt = logical % nbx;
+  nt = logical / nbx;
+}
 
 // ---------------------------------------------------------------- FP32/FP64
 template <typename T, int BM, int BN>
@@ -54,9 +72,9 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
   constexpr int VE = 16 / sizeof(T);  // elements per 16-byte vector
   constexpr int APAD = lds_pad(BM), BPAD = lds_pad(BN);
-  constexpr int NA = BK * BM / VE / 256;  // A vectors per thread per tile
-  constexpr int NB = BN * BK / VE / 256;  // B vectors per thread per tile
-  static_assert(NA * VE * 256 == BK * BM && NB * VE * 256 == BN * BK, "tile/thread mismatch");
+  constexpr int AV = BK * BM / VE, BV = BN * BK / VE;  // 16-byte vectors per tile
+  constexpr int NA = (AV + 255) / 256, NB = (BV + 255) / 256;  // per thread
+  static_assert(BM % 32 == 0 && BN % 32 == 0, "2x2 waves of 16x16 blocks");
   typedef typename Mfma4<T>::acc_t acc_t;
   struct alignas(16) Vec { T v[VE]; };
 
@@ -67,7 +85,9 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
   const T* __restrict__ B = static_cast<const T*>(g.B);
   T* __restrict__ C = static_cast<T*>(g.C);
   const int Npad = g.Npad, ncols = g.ncols;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  int mt, nt;
+  xcd_tile(mt, nt);
+  const int m0 = mt * BM, n0 = nt * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
 
@@ -78,7 +98,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
       const int idx = tid + i * 256;
       const int kk = idx / (BM / VE), mv = idx % (BM / VE);
       const int m = m0 + mv * VE;
-      if (m < Npad) {
+      if (idx < AV && m < Npad) {
         ra[i] = *reinterpret_cast<const Vec*>(A + (size_t)(k0 + kk) * Npad + m);
       } else {
 #pragma unroll
@@ -90,7 +110,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
       const int idx = tid + i * 256;
       const int kv = idx % (BK / VE), nn = idx / (BK / VE);
       const int n = n0 + nn;
-      if (n < ncols) {
+      if (idx < BV && n < ncols) {
         rb[i] = *reinterpret_cast<const Vec*>(B + (size_t)n * Npad + k0 + kv * VE);
       } else {
 #pragma unroll
@@ -103,14 +123,16 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
     for (int i = 0; i < NA; ++i) {
       const int idx = tid + i * 256;
       const int kk = idx / (BM / VE), mv = idx % (BM / VE);
-      *reinterpret_cast<Vec*>(&As[buf][kk][mv * VE]) = ra[i];
+      if (idx < AV) *reinterpret_cast<Vec*>(&As[buf][kk][mv * VE]) = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int idx = tid + i * 256;
       const int kv = idx % (BK / VE), nn = idx / (BK / VE);
+      if (idx < BV) {
 #pragma unroll
-      for (int e = 0; e < VE; ++e) Bs[buf][kv * VE + e][nn] = rb[i].v[e];
+        for (int e = 0; e < VE; ++e) Bs[buf][kv * VE + e][nn] = rb[i].v[e];
+      }
     }
   };
 
@@ -148,22 +170,22 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
     }
   }
 
-  // epilogue: lane holds rows 4*(lane/16)+r of column lane%16 of each 16x16 block
+  // epilogue: each 16x16 block lies inside [0, Npad) or wholly outside it
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
-    const int m = m0 + wm * WM + i * 16 + (lane >> 4) * 4;
-    if (m >= Npad) continue;
+    const int mb = m0 + wm * WM + i * 16;
+    if (mb >= Npad) continue;
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int n = n0 + wn * WN + j * 16 + (lane & 15);
       if (n >= ncols) continue;
-      T* c = C + (size_t)n * Npad + m;
+      T* c = C + (size_t)n * Npad + mb;
       if (g.mode == EPI_ADD) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) c[r] += acc[i][j][r];
+        for (int r = 0; r < 4; ++r) c[Mfma4<T>::row(lane, r)] += acc[i][j][r];
       } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) c[r] = acc[i][j][r];
+        for (int r = 0; r < 4; ++r) c[Mfma4<T>::row(lane, r)] = acc[i][j][r];
       }
     }
   }
@@ -196,9 +218,9 @@ __global__ void __launch_bounds__(256) gemm_lp_kernel(GemmArgs g) {
   constexpr int BK = 32;
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
   constexpr int KP = BK + 8;  // LDS row stride (elements): 80 bytes
-  constexpr int NA = BM * BK / 8 / 256;
-  constexpr int NB = BN * BK / 8 / 256;
-  static_assert(NA * 8 * 256 == BM * BK && NB * 8 * 256 == BN * BK, "tile/thread mismatch");
+  constexpr int AV = BM * BK / 8, BV = BN * BK / 8;  // 8-element vectors per tile
+  constexpr int NA = (AV + 255) / 256, NB = (BV + 255) / 256;
+  static_assert(BM % 32 == 0 && BN % 32 == 0, "2x2 waves of 16x16 blocks");
   typedef typename Mfma32<L>::vec_t vec_t;
 
   __shared__ L As[2][BM][KP];
@@ -209,7 +231,9 @@ __global__ void __launch_bounds__(256) gemm_lp_kernel(GemmArgs g) {
   const float* __restrict__ B = static_cast<const float*>(g.B);
   float* __restrict__ C = static_cast<float*>(g.C);
   const int Npad = g.Npad, ncols = g.ncols;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  int mt, nt;
+  xcd_tile(mt, nt);
+  const int m0 = mt * BM, n0 = nt * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
 
@@ -231,7 +255,7 @@ __global__ void __launch_bounds__(256) gemm_lp_kernel(GemmArgs g) {
       const int idx = tid + i * 256;
       const int mm = idx / (BK / 8), kv = idx % (BK / 8);
       const int m = m0 + mm, k = k0 + kv * 8;
-      if (m < Npad && k < Npad) {
+      if (idx < AV && m < Npad && k < Npad) {
         ra[i] = *reinterpret_cast<const vec_t*>(A + (size_t)m * Npad + k);
       } else {
 #pragma unroll
@@ -243,7 +267,7 @@ __global__ void __launch_bounds__(256) gemm_lp_kernel(GemmArgs g) {
       const int idx = tid + i * 256;
       const int nn = idx / (BK / 8), kv = idx % (BK / 8);
       const int n = n0 + nn, k = k0 + kv * 8;
-      if (n < ncols && k < Npad) {
+      if (idx < BV && n < ncols && k < Npad) {
         const float4 lo = *reinterpret_cast<const float4*>(B + (size_t)n * Npad + k);
         const float4 hi = *reinterpret_cast<const float4*>(B + (size_t)n * Npad + k + 4);
         const float s = sc_in[nn];
@@ -266,13 +290,13 @@ __global__ void __launch_bounds__(256) gemm_lp_kernel(GemmArgs g) {
     for (int i = 0; i < NA; ++i) {
       const int idx = tid + i * 256;
       const int mm = idx / (BK / 8), kv = idx % (BK / 8);
-      *reinterpret_cast<vec_t*>(&As[buf][mm][kv * 8]) = ra[i];
+      if (idx < AV) *reinterpret_cast<vec_t*>(&As[buf][mm][kv * 8]) = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int idx = tid + i * 256;
       const int nn = idx / (BK / 8), kv = idx % (BK / 8);
-      *reinterpret_cast<vec_t*>(&Bs[buf][nn][kv * 8]) = rb[i];
+      if (idx < BV) *reinterpret_cast<vec_t*>(&Bs[buf][nn][kv * 8]) = rb[i];
     }
   };
 
@@ -335,10 +359,17 @@ __global__ void __launch_bounds__(256) gemm_lp_kernel(GemmArgs g) {
 struct TileShape {
   int bm, bn;
 };
-static const TileShape kTiles[] = {{64, 64}, {64, 128}, {128, 64}, {128, 128}};
+static const TileShape kTiles[] = {{64, 64},  {64, 128}, {128, 64}, {128, 128},
+                                   {96, 64},  {96, 128}, {224, 32}, {224, 64}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 int gemm_num_tiles(int) { return kNumTiles; }
+
+void gemm_tile_shape(int tile, int* bm, int* bn) {
+  const bool ok = tile >= 0 && tile < kNumTiles;
+  *bm = ok ? kTiles[tile].bm : 0;
+  *bn = ok ? kTiles[tile].bn : 0;
+}
 
 template <typename T, int BM, int BN>
 static hipError_t run_gemm(const GemmArgs& g, hipStream_t st) {
@@ -372,6 +403,10 @@ hipError_t launch_gemm(int kind, int tile, const GemmArgs& g, hipStream_t st) {
     case 1: return run_kind<64, 128>(kind, g, st);
     case 2: return run_kind<128, 64>(kind, g, st);
     case 3: return run_kind<128, 128>(kind, g, st);
+    case 4: return run_kind<96, 64>(kind, g, st);
+    case 5: return run_kind<96, 128>(kind, g, st);
+    case 6: return run_kind<224, 32>(kind, g, st);
+    case 7: return run_kind<224, 64>(kind, g, st);
     default: return hipErrorInvalidValue;
   }
 }

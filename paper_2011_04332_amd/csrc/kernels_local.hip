@@ -9,11 +9,13 @@
 //     + w_v (Pv - x)
 // where Ps/Pa are the strain/area projections of F_t(q), Pb the bending
 // projection of y_e(q) = sum_r K_e[r] q_r and Pv the closest point of q on the
-// rest-volume surface. Element contributions are staged in LDS and gathered
-// per vertex through CSR incidence lists in a fixed order (no atomics), so
-// results are bitwise reproducible. Triangles and hinges are processed in
-// chunks sized to the LDS budget; chunking does not change the summation
-// order.
+// rest-volume surface.
+//
+// LDS holds the cell's vertices as 16/32-byte records (one vector read per
+// vertex), and the per-element contributions, which each vertex then gathers
+// through fixed-width incidence lists in a fixed order (no atomics): results
+// are bitwise reproducible. Triangles and hinges go through LDS in chunks
+// sized to the budget; chunking does not change the summation order.
 #include <algorithm>
 
 #include "device_utils.h"
@@ -22,16 +24,28 @@
 namespace npfem {
 
 template <typename T>
-struct LocalLaunch {
-  LocalArgs<T> a;
-  int tch;   // triangles per LDS chunk
-  int hch;   // hinges per LDS chunk
+struct alignas(4 * sizeof(T)) V4 {
+  T x, y, z, w;
 };
 
 template <typename T>
-__device__ __forceinline__ T rsqrt_t(T x) {
-  return T(1) / sqrt(x);
-}
+struct alignas(2 * sizeof(T)) V2 {
+  T x, y;
+};
+
+template <typename T>
+struct LocalLaunch {
+  LocalArgs<T> a;
+  int tch;  // triangles per LDS chunk
+  int hch;  // hinges per LDS chunk
+};
+
+// FP32 uses the hardware square root and reciprocal (about 1 ulp); FP64 keeps
+// the correctly rounded library forms.
+__device__ __forceinline__ float f_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double f_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float f_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double f_rcp(double x) { return 1.0 / x; }
 
 // Strain (polar factor) and area projections of a 3x2 deformation gradient.
 // S = F^T F = [[a, b], [b, c]], sigma1^2 sigma2^2 = |f0 x f1|^2.
@@ -51,36 +65,38 @@ __device__ __forceinline__ void project_triangle(const T (&f)[3][2], T (&ps)[3][
   const T nz = f[0][0] * f[1][1] - f[1][0] * f[0][1];
   const T det = nx * nx + ny * ny + nz * nz;
   const T hd = (a - c) * T(0.5);
-  const T rr = sqrt(hd * hd + b * b);
+  const T rr = f_sqrt(hd * hd + b * b);
   const T l1 = (a + c) * T(0.5) + rr;
-  const T s1 = sqrt(l1);
-  const T s12 = sqrt(det);
-  const T s2 = s12 / s1;
+  const T s1 = f_sqrt(l1);
+  const T s12 = f_sqrt(det);
+  const T is1 = f_rcp(s1);
+  const T s2 = s12 * is1;
   if (!(s2 > T(1e-12) * s1) || !isfinite(l1)) bad = 1;
   // polar factor
-  const T inv = T(1) / (s12 * (s1 + s2));
+  const T inv = f_rcp(s12 * (s1 + s2));
   const T m00 = (c + s12) * inv, m01 = -b * inv, m11 = (a + s12) * inv;
   // area root
-  T t = sqrt(s1 / s2);
+  T t = f_sqrt(s1 * f_rcp(s2));
 #pragma unroll
   for (int it = 0; it < NEWTON; ++it) {
     const T t2 = t * t;
     const T p = t2 * t * (t - s1) + s2 * t - T(1);
     const T dp = t2 * (T(4) * t - T(3) * s1) + s2;
-    t -= p / dp;
+    t -= p * f_rcp(dp);
   }
   if (!(t > T(0)) || !isfinite(t)) bad = 1;
-  const T al1 = t / s1;
-  const T al2 = T(1) / (t * s2);
+  const T al1 = t * is1;
+  const T al2 = f_rcp(t * s2);
   T cs = T(1), sn = T(0);
   if (rr > T(0)) {
-    const T c2 = hd / rr, s2a = b / rr;
+    const T irr = f_rcp(rr);
+    const T c2 = hd * irr, s2a = b * irr;
     if (c2 >= T(0)) {
-      cs = sqrt((T(1) + c2) * T(0.5));
-      sn = s2a / (T(2) * cs);
+      cs = f_sqrt((T(1) + c2) * T(0.5));
+      sn = s2a * T(0.5) * f_rcp(cs);
     } else {
-      sn = copysign(sqrt((T(1) - c2) * T(0.5)), s2a);
-      cs = s2a / (T(2) * sn);
+      sn = copysign(f_sqrt((T(1) - c2) * T(0.5)), s2a);
+      cs = s2a * T(0.5) * f_rcp(sn);
     }
   }
   const T da = al1 - al2;
@@ -94,25 +110,38 @@ __device__ __forceinline__ void project_triangle(const T (&f)[3][2], T (&ps)[3][
   }
 }
 
+template <typename T>
+__device__ __forceinline__ T comp(const V4<T>& v, int d) {
+  return d == 0 ? v.x : (d == 1 ? v.y : v.z);
+}
+
 template <typename T, int BLOCK, int VPT>
 __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
   extern __shared__ double smem_local[];
   constexpr int NW = BLOCK / kWave;
-  constexpr int NEWTON = sizeof(T) == 8 ? 5 : 4;
+  // Newton steps for the area root: the start sqrt(s1/s2) is exact to first
+  // order in the strain, so the error goes ~e^2 -> e^4 -> e^8 ...
+  constexpr int NEWTON = sizeof(T) == 8 ? 5 : 3;
   const LocalArgs<T>& a = L.a;
   const ClassView<T>& cv = a.cs.cv;
-  const int N = cv.N, Npad = cv.Npad, F = cv.F, E = cv.E;
+  const int N = cv.N, Npad = cv.Npad, F = cv.F, E = cv.E, DT = cv.DT, DH = cv.DH;
   const int tid = threadIdx.x;
   const int lc = blockIdx.x;
   const int cell = a.cs.cell0 + lc;
   const long long vb = a.cs.vert0 + (long long)lc * N;
   const long long cb = a.cs.elem0 + 3LL * lc * Npad;
-  const long long sumN = a.sumN;
+  // per-cell base pointers: everything below indexes with 32-bit offsets
+  const T* __restrict__ px = a.pos + vb;
+  const T* __restrict__ py = px + a.sumN;
+  const T* __restrict__ pz = py + a.sumN;
+  const T* __restrict__ dcol = a.delta + cb;
+  const T* __restrict__ ccol = a.cterm + cb;
+  T* __restrict__ rcol = a.rhs + cb;
 
   double* red = smem_local;  // 8 * NW doubles
-  T* qs = reinterpret_cast<T*>(smem_local + 8 * NW);
-  T* xs = qs + 3 * N;
-  T* work = xs + 3 * N;
+  V4<T>* qs = reinterpret_cast<V4<T>*>(smem_local + 8 * NW);
+  V4<T>* xs = qs + N;
+  T* work = reinterpret_cast<T*>(xs + N);
 
   T ws, wa, wb, wv;
   if (a.weights) {
@@ -130,14 +159,19 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
   double e_acc = 0.0;
   int bad = 0;
 
-  // ---- stage x and q = x + delta in LDS ----
+  // ---- stage x and q = x + delta ----
   for (int v = tid; v < N; v += BLOCK) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const T x = a.pos[d * sumN + vb + v];
-      xs[d * N + v] = x;
-      qs[d * N + v] = x + a.delta[cb + d * Npad + v];
-    }
+    V4<T> x, q;
+    x.x = px[v];
+    x.y = py[v];
+    x.z = pz[v];
+    x.w = T(0);
+    q.x = x.x + dcol[v];
+    q.y = x.y + dcol[Npad + v];
+    q.z = x.z + dcol[2 * Npad + v];
+    q.w = T(0);
+    xs[v] = x;
+    qs[v] = q;
   }
   __syncthreads();
 
@@ -149,12 +183,9 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
   // p <- q + lam grad V(p), lam = (V_rest - V(p) - grad V(p).(q - p)) / |grad V(p)|^2,
   // V(p) = (1/3) sum_v p_v . grad_v V(p) (Euler, V is cubic); sums in FP64.
   {
-    T* ps = work;
-    for (int v = tid; v < N; v += BLOCK) {
-      ps[v] = qs[v];
-      ps[N + v] = qs[N + v];
-      ps[2 * N + v] = qs[2 * N + v];
-    }
+    V4<T>* ps = reinterpret_cast<V4<T>*>(work);
+    for (int v = tid; v < N; v += BLOCK) ps[v] = qs[v];
+    if (tid == 0) ps[N] = V4<T>{T(0), T(0), T(0), T(0)};  // target of padding fan entries
     __syncthreads();
     T g[VPT][3];
     double lam = 0.0;
@@ -166,15 +197,15 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
         g[j][0] = g[j][1] = g[j][2] = T(0);
         if (v < N) {
           T gx = T(0), gy = T(0), gz = T(0);
-          const int e1 = cv.vt_ptr[v + 1];
-          for (int e = cv.vt_ptr[v]; e < e1; ++e) {
-            const int bc = cv.vt_fan[e];
-            const int vb2 = bc & 0xffff, vc = bc >> 16;
-            const T bx = ps[vb2], by = ps[N + vb2], bz = ps[2 * N + vb2];
-            const T cx = ps[vc], cy = ps[N + vc], cz = ps[2 * N + vc];
-            gx += by * cz - bz * cy;
-            gy += bz * cx - bx * cz;
-            gz += bx * cy - by * cx;
+          const int* __restrict__ fix = cv.vt_fan + v;
+#pragma unroll 6
+          for (int k = 0; k < DT; ++k) {
+            const int bc = fix[k * N];
+            const V4<T> pb = ps[bc & 0xffff];
+            const V4<T> pc = ps[bc >> 16];
+            gx += pb.y * pc.z - pb.z * pc.y;
+            gy += pb.z * pc.x - pb.x * pc.z;
+            gz += pb.x * pc.y - pb.y * pc.x;
           }
           gx *= T(1.0 / 6.0);
           gy *= T(1.0 / 6.0);
@@ -182,11 +213,13 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
           g[j][0] = gx;
           g[j][1] = gy;
           g[j][2] = gz;
-          const T px = ps[v], py = ps[N + v], pz = ps[2 * N + v];
-          s[0] += (double)px * gx + (double)py * gy + (double)pz * gz;
-          s[1] += (double)gx * gx + (double)gy * gy + (double)gz * gz;
-          s[2] += (double)gx * (double)(qs[v] - px) + (double)gy * (double)(qs[N + v] - py) +
-                  (double)gz * (double)(qs[2 * N + v] - pz);
+          // per-vertex dot products in the working precision, summed over
+          // the cell in FP64
+          const V4<T> p = ps[v];
+          const V4<T> q = qs[v];
+          s[0] += (double)(p.x * gx + p.y * gy + p.z * gz);
+          s[1] += (double)(gx * gx + gy * gy + gz * gz);
+          s[2] += (double)(gx * (q.x - p.x) + gy * (q.y - p.y) + gz * (q.z - p.z));
         }
       }
       block_sum<3>(s, red);  // barrier: all reads of ps are done
@@ -200,13 +233,22 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
       for (int j = 0; j < VPT; ++j) {
         const int v = tid + j * BLOCK;
         if (v < N) {
-          ps[v] = qs[v] + lt * g[j][0];
-          ps[N + v] = qs[N + v] + lt * g[j][1];
-          ps[2 * N + v] = qs[2 * N + v] + lt * g[j][2];
+          const V4<T> q = qs[v];
+          V4<T> p;
+          p.x = q.x + lt * g[j][0];
+          p.y = q.y + lt * g[j][1];
+          p.z = q.z + lt * g[j][2];
+          p.w = T(0);
+          ps[v] = p;
         }
       }
       __syncthreads();
-      const bool conv = fabs(lam_new - lam) <= a.vol_tol * fabs(lam_new);
+      // settled when the last change of lam moves the cell by less than a
+      // fraction of the correction itself or, absolutely, than an RMS
+      // vertex displacement of vol_abs (|dp|_2 = |d lam| |grad V|_2)
+      const double gn = sqrt(s[1]);
+      const bool conv = fabs(lam_new - lam) * gn <=
+                        fmax(a.vol_tol * fabs(lam_new) * gn, a.vol_abs);
       lam = lam_new;
       if (conv) break;
     }
@@ -214,14 +256,13 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
       if (v < N) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          const T p = ps[d * N + v];
-          acc[j][d] += wv * (p - xs[d * N + v]);
-          if (want_energy) {
-            const double dq = (double)qs[d * N + v] - (double)p;
-            e_acc += 0.5 * (double)wv * dq * dq;
-          }
+        const V4<T> p = ps[v], x = xs[v], q = qs[v];
+        acc[j][0] += wv * (p.x - x.x);
+        acc[j][1] += wv * (p.y - x.y);
+        acc[j][2] += wv * (p.z - x.z);
+        if (want_energy) {
+          const double d0 = (double)q.x - p.x, d1 = (double)q.y - p.y, d2 = (double)q.z - p.z;
+          e_acc += 0.5 * (double)wv * (d0 * d0 + d1 * d1 + d2 * d2);
         }
       }
     }
@@ -233,18 +274,21 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
     const int nt = min(L.tch, F - base);
     for (int t = base + tid; t < base + nt; t += BLOCK) {
       const int4 id = cv.tri_v[t];
-      const T* rec = cv.tri_rec + 8 * t;
-      const T g00 = rec[0], g01 = rec[1], g10 = rec[2], g11 = rec[3], g20 = rec[4], g21 = rec[5];
-      const T area = rec[6];
+      const V4<T> r0 = reinterpret_cast<const V4<T>*>(cv.tri_rec)[2 * t];
+      const V4<T> r1 = reinterpret_cast<const V4<T>*>(cv.tri_rec)[2 * t + 1];
+      const T g00 = r0.x, g01 = r0.y, g10 = r0.z, g11 = r0.w, g20 = r1.x, g21 = r1.y;
+      const T area = r1.z;
+      const V4<T> qa = qs[id.x], qb = qs[id.y], qc = qs[id.z];
+      const V4<T> xa = xs[id.x], xb = xs[id.y], xc = xs[id.z];
       T fq[3][2], fx[3][2];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const T qa = qs[d * N + id.x], qb = qs[d * N + id.y], qc = qs[d * N + id.z];
-        const T xa = xs[d * N + id.x], xb = xs[d * N + id.y], xc = xs[d * N + id.z];
-        fq[d][0] = qa * g00 + qb * g10 + qc * g20;
-        fq[d][1] = qa * g01 + qb * g11 + qc * g21;
-        fx[d][0] = xa * g00 + xb * g10 + xc * g20;
-        fx[d][1] = xa * g01 + xb * g11 + xc * g21;
+        const T q0 = comp(qa, d), q1 = comp(qb, d), q2 = comp(qc, d);
+        const T x0 = comp(xa, d), x1 = comp(xb, d), x2 = comp(xc, d);
+        fq[d][0] = q0 * g00 + q1 * g10 + q2 * g20;
+        fq[d][1] = q0 * g01 + q1 * g11 + q2 * g21;
+        fx[d][0] = x0 * g00 + x1 * g10 + x2 * g20;
+        fx[d][1] = x0 * g01 + x1 * g11 + x2 * g21;
       }
       T ps[3][2], pa[3][2];
       project_triangle<T, NEWTON>(fq, ps, pa, bad);
@@ -272,19 +316,33 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
       }
     }
     __syncthreads();
+    const bool whole = (nt == F);  // one chunk: every entry is in range
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
       if (v < N) {
-        const int e1 = cv.vt_ptr[v + 1];
-        for (int e = cv.vt_ptr[v]; e < e1; ++e) {
-          const int t = cv.vt_tri[e] - base;
-          if (t < 0 || t >= nt) continue;
-          const T ga = cv.vt_g[2 * e], gb = cv.vt_g[2 * e + 1];
-          const T* w = work + 6 * t;
-          acc[j][0] += ga * w[0] + gb * w[1];
-          acc[j][1] += ga * w[2] + gb * w[3];
-          acc[j][2] += ga * w[4] + gb * w[5];
+        const int* __restrict__ tix = cv.vt_tri + v;
+        const V2<T>* __restrict__ gix = reinterpret_cast<const V2<T>*>(cv.vt_g) + v;
+        if (whole) {
+#pragma unroll 6
+          for (int k = 0; k < DT; ++k) {
+            const int t = tix[k * N];
+            const V2<T> g2 = gix[k * N];
+            const T* w = work + 6 * t;
+            acc[j][0] += g2.x * w[0] + g2.y * w[1];
+            acc[j][1] += g2.x * w[2] + g2.y * w[3];
+            acc[j][2] += g2.x * w[4] + g2.y * w[5];
+          }
+        } else {
+          for (int k = 0; k < DT; ++k) {
+            const int t = tix[k * N] - base;
+            const V2<T> g2 = gix[k * N];
+            if (t < 0 || t >= nt) continue;
+            const T* w = work + 6 * t;
+            acc[j][0] += g2.x * w[0] + g2.y * w[1];
+            acc[j][1] += g2.x * w[2] + g2.y * w[3];
+            acc[j][2] += g2.x * w[4] + g2.y * w[5];
+          }
         }
       }
     }
@@ -294,46 +352,66 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
   // ---- hinges: bending ----
   for (int base = 0; base < E; base += L.hch) {
     const int ne = min(L.hch, E - base);
+    V4<T>* ys = reinterpret_cast<V4<T>*>(work);
     for (int e = base + tid; e < base + ne; e += BLOCK) {
       const int4 id = cv.hin_v[e];
-      const T* rec = cv.hin_rec + 8 * e;
-      const T k0 = rec[0], k1 = rec[1], k2 = rec[2], k3 = rec[3], ce = rec[4], rr = rec[5];
+      const V4<T> r0 = reinterpret_cast<const V4<T>*>(cv.hin_rec)[2 * e];
+      const V4<T> r1 = reinterpret_cast<const V4<T>*>(cv.hin_rec)[2 * e + 1];
+      const T k0 = r0.x, k1 = r0.y, k2 = r0.z, k3 = r0.w, ce = r1.x, rr = r1.y;
+      const V4<T> qi = qs[id.x], qj = qs[id.y], qk = qs[id.z], ql = qs[id.w];
+      const V4<T> xi = xs[id.x], xj = xs[id.y], xk = xs[id.z], xl = xs[id.w];
       T yq[3], yx[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        yq[d] = k0 * qs[d * N + id.x] + k1 * qs[d * N + id.y] + k2 * qs[d * N + id.z] +
-                k3 * qs[d * N + id.w];
-        yx[d] = k0 * xs[d * N + id.x] + k1 * xs[d * N + id.y] + k2 * xs[d * N + id.z] +
-                k3 * xs[d * N + id.w];
+        yq[d] = k0 * comp(qi, d) + k1 * comp(qj, d) + k2 * comp(qk, d) + k3 * comp(ql, d);
+        yx[d] = k0 * comp(xi, d) + k1 * comp(xj, d) + k2 * comp(xk, d) + k3 * comp(xl, d);
       }
       const T n2 = yq[0] * yq[0] + yq[1] * yq[1] + yq[2] * yq[2];
-      const T sc = n2 > T(0) ? rr / sqrt(n2) : T(1);
+      const T sc = n2 > T(0) ? rr * f_rcp(f_sqrt(n2)) : T(1);
       const T wc = wb * ce;
-      T* w = work + 3 * (e - base);
-      double eb = 0.0;
+      V4<T> y;
+      y.x = wc * (sc * yq[0] - yx[0]);
+      y.y = wc * (sc * yq[1] - yx[1]);
+      y.z = wc * (sc * yq[2] - yx[2]);
+      y.w = T(0);
+      ys[e - base] = y;
+      if (want_energy) {
+        double eb = 0.0;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const T pb = sc * yq[d];
-        w[d] = wc * (pb - yx[d]);
-        const double u = (double)yq[d] - (double)pb;
-        eb += u * u;
+        for (int d = 0; d < 3; ++d) {
+          const double u = (double)yq[d] - (double)(sc * yq[d]);
+          eb += u * u;
+        }
+        e_acc += 0.5 * (double)wc * eb;
       }
-      if (want_energy) e_acc += 0.5 * (double)wc * eb;
     }
     __syncthreads();
+    const bool whole = (ne == E);
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
       if (v < N) {
-        const int e1 = cv.vh_ptr[v + 1];
-        for (int e = cv.vh_ptr[v]; e < e1; ++e) {
-          const int hh = cv.vh_hin[e] - base;
-          if (hh < 0 || hh >= ne) continue;
-          const T kk = cv.vh_k[e];
-          const T* w = work + 3 * hh;
-          acc[j][0] += kk * w[0];
-          acc[j][1] += kk * w[1];
-          acc[j][2] += kk * w[2];
+        const int* __restrict__ hix = cv.vh_hin + v;
+        const T* __restrict__ kix = cv.vh_k + v;
+        if (whole) {
+#pragma unroll 4
+          for (int k = 0; k < DH; ++k) {
+            const V4<T> y = ys[hix[k * N]];
+            const T kk = kix[k * N];
+            acc[j][0] += kk * y.x;
+            acc[j][1] += kk * y.y;
+            acc[j][2] += kk * y.z;
+          }
+        } else {
+          for (int k = 0; k < DH; ++k) {
+            const int hh = hix[k * N] - base;
+            const T kk = kix[k * N];
+            if (hh < 0 || hh >= ne) continue;
+            const V4<T> y = ys[hh];
+            acc[j][0] += kk * y.x;
+            acc[j][1] += kk * y.y;
+            acc[j][2] += kk * y.z;
+          }
         }
       }
     }
@@ -343,6 +421,7 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
   // ---- r = inertia + elastic contributions; zero padding rows ----
   float cmax[3] = {0.f, 0.f, 0.f};
   const double hm = a.h * a.h / a.m;
+  const bool want_max = a.colmax != nullptr;
 #pragma unroll
   for (int j = 0; j <= VPT; ++j) {
     const int v = tid + j * BLOCK;
@@ -351,16 +430,16 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
       for (int d = 0; d < 3; ++d) {
         T r = T(0);
         if (v < N) {
-          const T ct = a.cterm[cb + d * Npad + v];
+          const T ct = ccol[d * Npad + v];
           r = ct + acc[j < VPT ? j : VPT - 1][d];
           if (want_energy) {
             // (m/2h^2) |q - s|^2 with q - s = delta - (h^2/m) cterm
-            const double dd = (double)a.delta[cb + d * Npad + v] - hm * (double)ct;
+            const double dd = (double)dcol[d * Npad + v] - hm * (double)ct;
             e_acc += 0.5 * (a.m / (a.h * a.h)) * dd * dd;
           }
         }
-        cmax[d] = fmaxf(cmax[d], fabsf((float)r));
-        a.rhs[cb + d * Npad + v] = r;
+        if (want_max) cmax[d] = fmaxf(cmax[d], fabsf((float)r));
+        rcol[d * Npad + v] = r;
       }
     }
   }
@@ -383,20 +462,22 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
   if (__syncthreads_or(bad) && tid == 0) atomicOr(a.status, ST_NONFINITE);
 }
 
+// LDS: reductions, q and x as 4-component records, and a work region that
+// holds the volume iterate p (N records plus a zero record) or one chunk of
+// triangle (6 values) or hinge (4 values) contributions.
 template <typename T>
 size_t local_smem_bytes_chunks(const ClassView<T>& cv, int block, int* tch, int* hch) {
-  const size_t fixed = 8 * sizeof(double) * (block / kWave) + sizeof(T) * 6 * (size_t)cv.N;
-  // element chunk budget: the larger of 3N (volume iterate) and what fits in
-  // the remaining LDS, capped by the element counts
+  const size_t fixed = 8 * sizeof(double) * (block / kWave) + sizeof(T) * 8 * (size_t)cv.N;
   const size_t max_total = 160 * 1024;
-  size_t work_elems = 3 * (size_t)cv.N;
-  size_t want = std::max<size_t>(6 * (size_t)cv.F, 3 * (size_t)cv.E);
-  size_t avail = max_total > fixed ? (max_total - fixed) / sizeof(T) : 0;
-  // keep a margin so two workgroups can share a CU when the mesh is small
-  size_t budget = std::min(want, std::max(work_elems, std::min(avail, (size_t)16384)));
-  if (budget < work_elems) budget = work_elems;
-  int t = (int)std::min<size_t>(cv.F, budget / 6);
-  int h = (int)std::min<size_t>(cv.E, budget / 3);
+  const size_t work_min = 4 * ((size_t)cv.N + 1);
+  const size_t want = std::max<size_t>(6 * (size_t)cv.F, 4 * (size_t)cv.E);
+  const size_t avail = max_total > fixed ? (max_total - fixed) / sizeof(T) : 0;
+  // cap the chunk budget so that small meshes leave room for several
+  // workgroups per CU
+  size_t budget = std::min(want, std::max(work_min, std::min(avail, (size_t)16384)));
+  if (budget < work_min) budget = work_min;
+  const int t = (int)std::min<size_t>(cv.F, budget / 6);
+  const int h = (int)std::min<size_t>(cv.E, budget / 4);
   if (tch) *tch = std::max(t, 1);
   if (hch) *hch = std::max(h, 1);
   return fixed + sizeof(T) * budget;
@@ -440,6 +521,7 @@ hipError_t local_prepare(const ClassView<T>& cv, int block) {
   LocalFn<T> fn = pick_local<T>(cv.N, block);
   if (!fn) return hipErrorInvalidValue;
   const size_t smem = local_smem_bytes_chunks(cv, block, nullptr, nullptr);
+  if (smem > 160 * 1024) return hipErrorInvalidValue;
   if (smem > 64 * 1024)
     return hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)smem);
@@ -454,6 +536,7 @@ hipError_t launch_local(const LocalArgs<T>& a, int block, hipStream_t st) {
   LocalLaunch<T> L;
   L.a = a;
   const size_t smem = local_smem_bytes_chunks(a.cs.cv, block, &L.tch, &L.hch);
+  if (smem > 160 * 1024) return hipErrorInvalidValue;
   void* args[] = {&L};
   return hipLaunchKernel((const void*)fn, dim3(a.cs.n_cells), dim3(block), args, smem, st);
 }

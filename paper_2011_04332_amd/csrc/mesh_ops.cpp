@@ -180,6 +180,16 @@ int build_mesh_ops(const double* xyz, int n, const int32_t* tris, int nt, MeshOp
     vol6 += dot3(A, bc);
   }
   M.vol_rest = vol6 / 6.0;
+  {
+    double cen[3] = {0, 0, 0};
+    for (int i = 0; i < n; ++i)
+      for (int d = 0; d < 3; ++d) cen[d] += xyz[3 * i + d] / n;
+    for (int i = 0; i < n; ++i) {
+      double r[3];
+      sub3(&xyz[3 * i], cen, r);
+      M.radius = std::max(M.radius, norm3(r));
+    }
+  }
   if (!(M.vol_rest > 0.0)) {
     err = "enclosed volume is not positive (triangles must be counter-clockwise seen from outside)";
     return NPFEM_ERR_INVALID_ARG;

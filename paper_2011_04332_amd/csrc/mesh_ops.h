@@ -19,6 +19,7 @@ struct MeshOps {
   std::vector<double> cw;    // [E] 3 / (A1 + A2)
   std::vector<double> rr;    // [E] rest |y|
   double vol_rest = 0.0;
+  double radius = 0.0;       // max distance of a rest vertex from the rest centroid
   // vertex incidence (CSR, entries in ascending element order)
   std::vector<int> vt_ptr, vt_tri, vt_fan;
   std::vector<double> vt_g;  // [entries][2]

@@ -19,13 +19,17 @@ struct ClassView {
   const T* tri_rec;    // [F][8]: G (3x2 row-major), area, 0
   const int4* hin_v;   // [E] (i, j, k, l)
   const T* hin_rec;    // [E][8]: K[4], c, r_rest, 0, 0
-  const int* vt_ptr;   // [N+1] vertex -> incident triangle entries
-  const int* vt_tri;   // triangle index of each entry (ascending per vertex)
-  const T* vt_g;       // [entries][2] G row of the vertex in that triangle
-  const int* vt_fan;   // other two vertices (b | c << 16), (v, b, c) counter-clockwise
-  const int* vh_ptr;   // [N+1] vertex -> incident hinge entries
-  const int* vh_hin;   // hinge index of each entry (ascending per vertex)
-  const T* vh_k;       // stencil coefficient of the vertex in that hinge
+  // Vertex incidence padded to a fixed width (slot-major [slot][N], so that
+  // threads of consecutive vertices read consecutive words); entries of a
+  // vertex are in ascending element order, padding entries contribute zero.
+  int DT;              // max triangles per vertex
+  int DH;              // max hinges per vertex
+  const int* vt_tri;   // [DT][N] triangle index (0 in padding)
+  const T* vt_g;       // [DT][N][2] G row of the vertex in that triangle (0 in padding)
+  const int* vt_fan;   // [DT][N] other two vertices b | c << 16, (v, b, c) counter-clockwise;
+                       // padding N | N << 16 (a zero record in the kernel's LDS)
+  const int* vh_hin;   // [DH][N] hinge index (0 in padding)
+  const T* vh_k;       // [DH][N] stencil coefficient of the vertex (0 in padding)
   const int* lap_ptr;  // [N+1] CSR of the Laplacian pattern (diagonal included)
   const int* lap_col;
   const T* lap_t;      // sum_t A_t G_t G_t^T entries
@@ -66,7 +70,8 @@ struct LocalArgs {
   int* status;         // device flags
   double h, m;
   int max_vol_iter;
-  double vol_tol;
+  double vol_tol;      // relative settling test of the volume multiplier
+  double vol_abs;      // absolute test: |d lam| |grad V|_2 below this (length units)
 };
 
 enum EpilogueMode : int { EPI_SET = 0, EPI_ADD = 1, EPI_SPLIT_SET = 2, EPI_SPLIT_ADD = 3 };
@@ -109,6 +114,7 @@ hipError_t launch_volume(const ClassSlice<T>& cs, const T* pos, long long sumN, 
 // Global-step GEMM variants. kind: 0 = FP32, 1 = FP64, 2 = BF16, 3 = FP16.
 hipError_t launch_gemm(int kind, int tile, const GemmArgs& g, hipStream_t st);
 int gemm_num_tiles(int kind);
+void gemm_tile_shape(int tile, int* bm, int* bn);
 
 // FP64 Gauss-Jordan inverse of an SPD matrix in place (device, n x n,
 // leading dimension ld); *pivot_fail set non-zero if a pivot is <= 0.

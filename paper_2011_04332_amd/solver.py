@@ -79,7 +79,7 @@ class Batch:
 
     def __init__(self, meshes, cell_mesh, pos: torch.Tensor, vel: torch.Tensor, cell_weights=None,
                  precision="fp32", n_refine=-1, max_vol_iter=0, energy=False, graph=True,
-                 sync_check=False, kernel_timing=False, stream=None):
+                 sync_check=False, kernel_timing=False, autotune=False, stream=None):
         lib = _lib.load()
         code = precision_code(precision)
         dt_ = state_dtype(code)
@@ -106,6 +106,8 @@ class Batch:
             flags |= _lib.OPT_SYNC_CHECK
         if kernel_timing:
             flags |= _lib.OPT_KERNEL_TIMING
+        if autotune:
+            flags |= _lib.OPT_AUTOTUNE
         if stream is None:
             stream = torch.cuda.current_stream(pos.device)
         self.stream = stream
@@ -145,6 +147,17 @@ class Batch:
         out = np.empty(self.n_cells, dtype=np.float64)
         _lib.check(_lib.load().npfem_get_volume(self.handle, out.ctypes.data))
         return out
+
+    def config(self, cls=0):
+        """(local workgroup size, GEMM tile rows, GEMM tile cols, correction sweeps)."""
+        out = np.zeros(4, dtype=np.int32)
+        _lib.check(_lib.load().npfem_batch_config(self.handle, int(cls), out.ctypes.data))
+        return tuple(int(v) for v in out)
+
+    def set_config(self, cls, cfg):
+        """Pin (local workgroup size, GEMM tile rows, GEMM tile cols, sweeps or -1)."""
+        arr = np.ascontiguousarray(cfg, dtype=np.int32)
+        _lib.check(_lib.load().npfem_set_batch_config(self.handle, int(cls), arr.ctypes.data))
 
     def kernel_times(self, reset=False):
         """{kind: (total ms, launches)} accumulated from per-kernel HIP events."""

@@ -20,7 +20,7 @@ def as_precision(susp, dtype):
     from npfem_workload.suspensions import Suspension
     r = lambda a: a.astype(dtype).astype(np.float64)
     return Suspension(susp.classes, susp.cell_class, susp.origins, r(susp.x0), r(susp.v0),
-                      r(susp.forces), r(susp.weights), susp.dt, susp.n_iter, susp.n_steps,
+                      r(susp.forces), (susp.weights if susp.uniform_weights() else r(susp.weights)), susp.dt, susp.n_iter, susp.n_steps,
                       susp.name, dict(susp.extra))
 
 
