@@ -92,13 +92,68 @@ def _pin_threads():
         pass
 
 
-def algorithmic_work(s):
-    """Per-launch algorithmic work of the global GEMM (dense 2 N^2 per column)."""
-    flops = 0.0
+def class_counts(s):
     for k, mc in enumerate(s.classes):
         n_c = int((s.cell_class == k).sum())
-        flops += 2.0 * mc.n_verts ** 2 * 3 * n_c
-    return flops
+        F = int(mc.tris.shape[0])
+        yield n_c, mc.n_verts, F, 3 * F // 2
+
+
+def gemm_flops(s):
+    """Algorithmic FLOPs of one global-step launch: dense 2 N^2 per column,
+    3 columns per cell, N the real (unpadded) vertex count."""
+    return sum(2.0 * N * N * 3 * n_c for n_c, N, F, E in class_counts(s))
+
+
+# Algorithmic FLOPs of the local step per element (FMA = 2, add/mul/sqrt/rcp = 1),
+# counted from the operations it performs: strain + area projection and
+# contribution per triangle, bending per hinge, one volume pass per vertex
+# (36 per triangle for the corner cross products, 33 per vertex), the two
+# gathers (12 per triangle corner, 24 per hinge) and the final sum.
+TRI_FLOPS, HINGE_FLOPS = 251, 60
+VOL_TRI_FLOPS, VOL_VERT_FLOPS = 36, 33
+VOLUME_PASSES = 2  # the minimum the settling test needs
+
+
+def local_flops(s):
+    total = 0.0
+    for n_c, N, F, E in class_counts(s):
+        per_cell = (TRI_FLOPS * F + HINGE_FLOPS * E
+                    + VOLUME_PASSES * (VOL_TRI_FLOPS * F + VOL_VERT_FLOPS * N) + 6 * N
+                    + 12 * 3 * F + 24 * E + 3 * N)
+        total += n_c * per_cell
+    return total
+
+
+def local_bytes(s, elem=4):
+    """Algorithmic HBM bytes of one local-step launch: read x, delta and the
+    inertia term (3 N each), write the right-hand side (3 Npad)."""
+    return sum(n_c * elem * (9 * N + 3 * ((N + 15) // 16 * 16)) for n_c, N, F, E in class_counts(s))
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2011_04332_amd", "csrc")
+    for name in ("kernels_local.hip", "kernels_gemm.hip", "device_utils.h", "npfem_internal.h"):
+        with open(os.path.join(root, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary, if it was taken on the current kernel sources (else None)."""
+    import re
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        f"{workload}_{precision}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\s*(\{.*?\})\s*```", open(path).read(), re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    return d if d.get("kernel_source_sha256_16") == kernel_source_digest() else None
 
 
 def main():
@@ -187,25 +242,35 @@ def main():
         bt.sync_status()
         bitwise = bool(torch.equal(pos, x_timed))
         bt.close()
+        traffic = measured_traffic(a.workload, a.precision)
+        entries = {}
+        for kind in ("local", "global"):
+            ms, n = kt[kind]
+            avg_s = ms / n * 1e-3
+            if kind == "local":
+                work = local_flops(s)
+                peak = PEAK["fp64_matrix_TF"] if a.precision == "fp64" else PEAK["fp32_vector_TF"]
+                e = {"bound": "alu", "kernel": "local_kernel (projections + RHS gather)",
+                     "algorithmic_flops": work, "algorithmic_hbm_bytes": local_bytes(s),
+                     "alu_peak_without_packed_fp32": 78.6}
+            else:
+                work = gemm_flops(s)
+                peak = PEAK[f"{a.precision}_matrix_TF"]
+                e = {"bound": "mfma", "kernel": "gemm_kernel (global step)", "algorithmic_flops": work}
+            achieved = work / avg_s / 1e12
+            e.update({"achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                      "frac": round(achieved / peak, 4), "avg_launch_us": round(avg_s * 1e6, 2),
+                      "launches": n,
+                      "traffic": (traffic or {}).get(kind)})
+            entries[kind] = e
         dom = max(("local", "global"), key=lambda k: kt[k][0])
-        g_ms, g_n = kt["global"]
-        flops = algorithmic_work(s)
-        gemm_avg_s = g_ms / g_n * 1e-3
-        peak_tf = PEAK[f"{a.precision}_matrix_TF"]
-        achieved_tf = flops / gemm_avg_s / 1e12
-        roof = {
-            "bound": "mfma",
-            "kernel": "global-step GEMM (gemm_kernel)",
-            "achieved": round(achieved_tf, 3),
-            "peak": peak_tf,
-            "unit": "TFLOP/s",
-            "frac": round(achieved_tf / peak_tf, 4),
-            "traffic": None,
-            "avg_launch_us": round(gemm_avg_s * 1e6, 2),
+        roof = dict(entries[dom])
+        roof.update({
             "dominant_kernel": dom,
+            "other_kernel": entries["global" if dom == "local" else "local"],
             "kernel_ms_per_step": {k: round(v[0] / a.steps, 4) for k, v in kt.items()},
             "timing_pass_bitwise_equal": bitwise,
-        }
+        })
         print(f"[bench] kernel times (ms/step): {roof['kernel_ms_per_step']}", file=sys.stderr,
               flush=True)
 
