@@ -163,6 +163,41 @@ int npfem_create_batch(const npfem_mesh* meshes, int32_t n_meshes, const int32_t
  * NONFINITE (only with NPFEM_OPT_SYNC_CHECK), HIP, OOM. */
 int npfem_step(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter);
 
+/* Replaces the per-cell weights (host [n_cells][4]: stretch, area, bend,
+ * volume; NULL = each class's nominal material). The class operators stay
+ * those of the nominal material; cells whose weights differ are solved with
+ * correction sweeps against their own matrix (the sweep count follows from
+ * the largest deviation). Synchronises; the next step re-captures its graph.
+ * Errors: INVALID_ARG (non-finite or negative weights, or weights too far
+ * from nominal for the sweeps to converge), HIP. */
+int npfem_set_weights(npfem_batch b, const double* cell_weights);
+
+/* Differentiable rollout: n_steps calls of npfem_step under constant forces,
+ * storing (positions, velocities) before every ckpt_every-th step as
+ * checkpoints for npfem_rollout_adjoint (the time-step loop the adjoint
+ * reverses). Positions and velocities hold the final state on return.
+ * Errors: as npfem_step; INVALID_ARG for n_steps < 1 or ckpt_every outside
+ * [1, n_steps]; OOM. */
+int npfem_rollout(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter,
+                  int32_t n_steps, int32_t ckpt_every);
+
+/* Reverse-mode gradient of a scalar loss L(x_T, v_T) of the last rollout.
+ * Each checkpointed segment is recomputed storing every PD iterate, then the
+ * iterations and steps are reversed: per iteration one solve with the
+ * (symmetric) system matrix and one projection-VJP kernel.
+ *   dL_dx, dL_dv   device SoA [3][sum_N] (element type as pos), dL_dv may be NULL
+ *   dL_dw          device FP64 [n_cells][4]: dL/d(stretch, area, bend, volume)
+ *                  weights of each cell (may be NULL)
+ *   dL_df          device SoA [3][sum_N]: dL/d(ext_forces), constant forces
+ *                  (may be NULL)
+ *   dL_dx0, dL_dv0 device SoA [3][sum_N]: gradients w.r.t. the initial state
+ *                  (may be NULL)
+ * Synchronises. Positions and velocities are not modified. Not available for
+ * NPFEM_FP16_REFINE (INVALID_ARG). Errors: INVALID_ARG (no rollout, or dt or
+ * weights changed since), NONFINITE, HIP, OOM. */
+int npfem_rollout_adjoint(npfem_batch b, const void* dL_dx, const void* dL_dv, void* dL_dw,
+                          void* dL_df, void* dL_dx0, void* dL_dv0);
+
 /* Synchronises the batch stream, returns NPFEM_ERR_NONFINITE if any kernel
  * saw a NaN/Inf (in state, forces, or a per-cell FP64 reduction) since the
  * previous call, and clears the flag. */

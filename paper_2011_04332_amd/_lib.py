@@ -38,6 +38,9 @@ EXPORTED = [
     "npfem_mesh_system_matrix",
     "npfem_create_batch",
     "npfem_step",
+    "npfem_set_weights",
+    "npfem_rollout",
+    "npfem_rollout_adjoint",
     "npfem_sync_status",
     "npfem_get_energy",
     "npfem_get_volume",
@@ -94,6 +97,9 @@ def load() -> ctypes.CDLL:
     lib.npfem_create_batch.argtypes = [P, I32, P, I32, P, P, P, ctypes.POINTER(Options),
                                        ctypes.POINTER(P)]
     lib.npfem_step.argtypes = [P, P, D, I32]
+    lib.npfem_set_weights.argtypes = [P, P]
+    lib.npfem_rollout.argtypes = [P, P, D, I32, I32, I32]
+    lib.npfem_rollout_adjoint.argtypes = [P, P, P, P, P, P, P]
     lib.npfem_sync_status.argtypes = [P]
     lib.npfem_get_energy.argtypes = [P, P, I32, P]
     lib.npfem_get_volume.argtypes = [P, P]

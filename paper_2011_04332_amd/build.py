@@ -26,6 +26,7 @@ SOURCES = [
     "kernels_local.hip",
     "kernels_gemm.hip",
     "kernels_factor.hip",
+    "kernels_adjoint.hip",
 ]
 
 # Packed-FP32 VALU instructions are kept out of all device code: the compiler

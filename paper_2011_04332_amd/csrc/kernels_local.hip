@@ -19,19 +19,11 @@
 #include <algorithm>
 
 #include "device_utils.h"
+#include "local_common.h"
 #include "npfem_internal.h"
+#include "projections.h"
 
 namespace npfem {
-
-template <typename T>
-struct alignas(4 * sizeof(T)) V4 {
-  T x, y, z, w;
-};
-
-template <typename T>
-struct alignas(2 * sizeof(T)) V2 {
-  T x, y;
-};
 
 template <typename T>
 struct LocalLaunch {
@@ -40,88 +32,11 @@ struct LocalLaunch {
   int hch;  // hinges per LDS chunk
 };
 
-// FP32 uses the hardware square root and reciprocal (about 1 ulp); FP64 keeps
-// the correctly rounded library forms.
-__device__ __forceinline__ float f_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double f_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float f_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double f_rcp(double x) { return 1.0 / x; }
-
-// Strain (polar factor) and area projections of a 3x2 deformation gradient.
-// S = F^T F = [[a, b], [b, c]], sigma1^2 sigma2^2 = |f0 x f1|^2.
-//   polar:  F S^{-1/2},  S^{-1/2} = [[c + s, -b], [-b, a + s]] / (s (sigma1 + sigma2)),
-//           s = sigma1 sigma2 (closed-form square root of a 2x2 SPD matrix);
-//   area:   F V diag(t/sigma1, (1/t)/sigma2) V^T with t the positive root of
-//           t^4 - sigma1 t^3 + sigma2 t - 1 (Newton from sqrt(sigma1/sigma2))
-//           and V the eigenvectors of S (half-angle formulas).
-template <typename T, int NEWTON>
-__device__ __forceinline__ void project_triangle(const T (&f)[3][2], T (&ps)[3][2], T (&pa)[3][2],
-                                                 int& bad) {
-  const T a = f[0][0] * f[0][0] + f[1][0] * f[1][0] + f[2][0] * f[2][0];
-  const T b = f[0][0] * f[0][1] + f[1][0] * f[1][1] + f[2][0] * f[2][1];
-  const T c = f[0][1] * f[0][1] + f[1][1] * f[1][1] + f[2][1] * f[2][1];
-  const T nx = f[1][0] * f[2][1] - f[2][0] * f[1][1];
-  const T ny = f[2][0] * f[0][1] - f[0][0] * f[2][1];
-  const T nz = f[0][0] * f[1][1] - f[1][0] * f[0][1];
-  const T det = nx * nx + ny * ny + nz * nz;
-  const T hd = (a - c) * T(0.5);
-  const T rr = f_sqrt(hd * hd + b * b);
-  const T l1 = (a + c) * T(0.5) + rr;
-  const T s1 = f_sqrt(l1);
-  const T s12 = f_sqrt(det);
-  const T is1 = f_rcp(s1);
-  const T s2 = s12 * is1;
-  if (!(s2 > T(1e-12) * s1) || !isfinite(l1)) bad = 1;
-  // polar factor
-  const T inv = f_rcp(s12 * (s1 + s2));
-  const T m00 = (c + s12) * inv, m01 = -b * inv, m11 = (a + s12) * inv;
-  // area root
-  T t = f_sqrt(s1 * f_rcp(s2));
-#pragma unroll
-  for (int it = 0; it < NEWTON; ++it) {
-    const T t2 = t * t;
-    const T p = t2 * t * (t - s1) + s2 * t - T(1);
-    const T dp = t2 * (T(4) * t - T(3) * s1) + s2;
-    t -= p * f_rcp(dp);
-  }
-  if (!(t > T(0)) || !isfinite(t)) bad = 1;
-  const T al1 = t * is1;
-  const T al2 = f_rcp(t * s2);
-  T cs = T(1), sn = T(0);
-  if (rr > T(0)) {
-    const T irr = f_rcp(rr);
-    const T c2 = hd * irr, s2a = b * irr;
-    if (c2 >= T(0)) {
-      cs = f_sqrt((T(1) + c2) * T(0.5));
-      sn = s2a * T(0.5) * f_rcp(cs);
-    } else {
-      sn = copysign(f_sqrt((T(1) - c2) * T(0.5)), s2a);
-      cs = s2a * T(0.5) * f_rcp(sn);
-    }
-  }
-  const T da = al1 - al2;
-  const T n00 = al2 + da * cs * cs, n01 = da * cs * sn, n11 = al2 + da * sn * sn;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    ps[d][0] = f[d][0] * m00 + f[d][1] * m01;
-    ps[d][1] = f[d][0] * m01 + f[d][1] * m11;
-    pa[d][0] = f[d][0] * n00 + f[d][1] * n01;
-    pa[d][1] = f[d][0] * n01 + f[d][1] * n11;
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ T comp(const V4<T>& v, int d) {
-  return d == 0 ? v.x : (d == 1 ? v.y : v.z);
-}
-
 template <typename T, int BLOCK, int VPT>
 __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
   extern __shared__ double smem_local[];
   constexpr int NW = BLOCK / kWave;
-  // Newton steps for the area root: the start sqrt(s1/s2) is exact to first
-  // order in the strain, so the error goes ~e^2 -> e^4 -> e^8 ...
-  constexpr int NEWTON = sizeof(T) == 8 ? 5 : 3;
+  constexpr int NEWTON = sizeof(T) == 8 ? 4 : 3;  // area multiplier (projections.h)
   const LocalArgs<T>& a = L.a;
   const ClassView<T>& cv = a.cs.cv;
   const int N = cv.N, Npad = cv.Npad, F = cv.F, E = cv.E, DT = cv.DT, DH = cv.DH;
@@ -179,79 +94,11 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
 #pragma unroll
   for (int j = 0; j < VPT; ++j) acc[j][0] = acc[j][1] = acc[j][2] = T(0);
 
-  // ---- volume: closest point of q on {V(p) = V_rest} ----
-  // p <- q + lam grad V(p), lam = (V_rest - V(p) - grad V(p).(q - p)) / |grad V(p)|^2,
-  // V(p) = (1/3) sum_v p_v . grad_v V(p) (Euler, V is cubic); sums in FP64.
+  // ---- volume: closest point of q on {V(p) = V_rest} (local_common.h) ----
   {
     V4<T>* ps = reinterpret_cast<V4<T>*>(work);
-    for (int v = tid; v < N; v += BLOCK) ps[v] = qs[v];
-    if (tid == 0) ps[N] = V4<T>{T(0), T(0), T(0), T(0)};  // target of padding fan entries
-    __syncthreads();
     T g[VPT][3];
-    double lam = 0.0;
-    for (int it = 0; it < a.max_vol_iter; ++it) {
-      double s[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-      for (int j = 0; j < VPT; ++j) {
-        const int v = tid + j * BLOCK;
-        g[j][0] = g[j][1] = g[j][2] = T(0);
-        if (v < N) {
-          T gx = T(0), gy = T(0), gz = T(0);
-          const int* __restrict__ fix = cv.vt_fan + v;
-#pragma unroll 6
-          for (int k = 0; k < DT; ++k) {
-            const int bc = fix[k * N];
-            const V4<T> pb = ps[bc & 0xffff];
-            const V4<T> pc = ps[bc >> 16];
-            gx += pb.y * pc.z - pb.z * pc.y;
-            gy += pb.z * pc.x - pb.x * pc.z;
-            gz += pb.x * pc.y - pb.y * pc.x;
-          }
-          gx *= T(1.0 / 6.0);
-          gy *= T(1.0 / 6.0);
-          gz *= T(1.0 / 6.0);
-          g[j][0] = gx;
-          g[j][1] = gy;
-          g[j][2] = gz;
-          // per-vertex dot products in the working precision, summed over
-          // the cell in FP64
-          const V4<T> p = ps[v];
-          const V4<T> q = qs[v];
-          s[0] += (double)(p.x * gx + p.y * gy + p.z * gz);
-          s[1] += (double)(gx * gx + gy * gy + gz * gz);
-          s[2] += (double)(gx * (q.x - p.x) + gy * (q.y - p.y) + gz * (q.z - p.z));
-        }
-      }
-      block_sum<3>(s, red);  // barrier: all reads of ps are done
-      double lam_new = (cv.vol_rest - s[0] / 3.0 - s[2]) / s[1];
-      if (!isfinite(lam_new)) {
-        bad = 1;
-        lam_new = 0.0;
-      }
-      const T lt = T(lam_new);
-#pragma unroll
-      for (int j = 0; j < VPT; ++j) {
-        const int v = tid + j * BLOCK;
-        if (v < N) {
-          const V4<T> q = qs[v];
-          V4<T> p;
-          p.x = q.x + lt * g[j][0];
-          p.y = q.y + lt * g[j][1];
-          p.z = q.z + lt * g[j][2];
-          p.w = T(0);
-          ps[v] = p;
-        }
-      }
-      __syncthreads();
-      // settled when the last change of lam moves the cell by less than a
-      // fraction of the correction itself or, absolutely, than an RMS
-      // vertex displacement of vol_abs (|dp|_2 = |d lam| |grad V|_2)
-      const double gn = sqrt(s[1]);
-      const bool conv = fabs(lam_new - lam) * gn <=
-                        fmax(a.vol_tol * fabs(lam_new) * gn, a.vol_abs);
-      lam = lam_new;
-      if (conv) break;
-    }
+    volume_project<T, BLOCK, VPT>(cv, qs, ps, red, g, a.max_vol_iter, a.vol_tol, a.vol_abs, bad);
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
@@ -290,8 +137,10 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
         fx[d][0] = x0 * g00 + x1 * g10 + x2 * g20;
         fx[d][1] = x0 * g01 + x1 * g11 + x2 * g21;
       }
-      T ps[3][2], pa[3][2];
-      project_triangle<T, NEWTON>(fq, ps, pa, bad);
+      TriProj<T> P;
+      project_triangle<T, NEWTON>(fq, P, bad);
+      const T(&ps)[3][2] = P.ps;
+      const T(&pa)[3][2] = P.pa;
       T* w = work + 6 * (t - base);
 #pragma unroll
       for (int d = 0; d < 3; ++d) {

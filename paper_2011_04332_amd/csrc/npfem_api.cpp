@@ -114,6 +114,7 @@ struct npfem_batch_s {
   void* weights_dev = nullptr;
   bool per_cell = false;
   std::vector<double> weights_host;  // [n_cells][4] effective weights
+  std::vector<int> cell_class;       // [n_cells] mesh class of each cell
   double dt = -1.0;
   int n_refine = 0;
   bool tuned = false;
@@ -121,6 +122,17 @@ struct npfem_batch_s {
   const void* graph_forces = nullptr;
   int graph_iters = 0;
   std::vector<void*> allocs;
+  // differentiable rollout: checkpoints and recompute workspace
+  void* ckpt = nullptr;          // [n_seg][2][3][sumN] positions then velocities
+  size_t ckpt_bytes = 0;
+  void* tape = nullptr;          // [ckpt_every][3 sumN + (n_iter + 1) total_elems]
+  size_t tape_bytes = 0;
+  void* adj_work = nullptr;      // xs, vs, xbar, vbar (3 sumN each); lam, gbar, sbar (columns)
+  size_t adj_work_bytes = 0;
+  int ro_steps = 0, ro_iter = 0, ro_every = 0;
+  double ro_dt = 0.0;
+  const void* ro_forces = nullptr;
+  bool ro_valid = false;
   // kernel timing (NPFEM_OPT_KERNEL_TIMING): event pairs around launches
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, int>> ev_pending;  // (kind, start event index)
@@ -167,6 +179,9 @@ struct npfem_batch_s {
       if (c.op) hipFree(c.op);
     }
     for (void* p : allocs) hipFree(p);
+    if (ckpt) hipFree(ckpt);
+    if (tape) hipFree(tape);
+    if (adj_work) hipFree(adj_work);
     if (cap_stream) hipStreamDestroy(cap_stream);
   }
 };
@@ -365,6 +380,44 @@ int choose_refine(npfem_batch_s* b, double dt, int* out) {
   return NPFEM_OK;
 }
 
+// Sets the effective per-cell weights (NULL = nominal), uploads them when any
+// differs from its class material and re-derives the correction sweeps.
+int apply_weights(npfem_batch_s* b, const double* cell_weights) {
+  const int n = b->n_cells;
+  b->weights_host.resize(4 * (size_t)n);
+  b->per_cell = false;
+  for (int c = 0; c < n; ++c) {
+    const npfem_material& m = b->cls[b->cell_class[c]].mat;
+    const double nom[4] = {m.w_stretch, m.w_area, m.w_bend, m.w_volume};
+    for (int i = 0; i < 4; ++i) {
+      const double w = cell_weights ? cell_weights[4 * (size_t)c + i] : nom[i];
+      b->weights_host[4 * (size_t)c + i] = w;
+      if (w != nom[i]) b->per_cell = true;
+    }
+  }
+  if (b->per_cell) {
+    const size_t tsz = b->fp64 ? sizeof(double) : sizeof(float);
+    if (!b->weights_dev) {
+      const int rc = dalloc(b, &b->weights_dev, tsz * 4 * (size_t)n, "weights");
+      if (rc) return rc;
+    }
+    hipError_t e;
+    if (b->fp64) {
+      e = hipMemcpy(b->weights_dev, b->weights_host.data(), 8 * 4 * (size_t)n,
+                    hipMemcpyHostToDevice);
+    } else {
+      std::vector<float> wf(b->weights_host.begin(), b->weights_host.end());
+      e = hipMemcpy(b->weights_dev, wf.data(), 4 * 4 * (size_t)n, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return hip_fail(e, "weights upload");
+  }
+  if (b->dt > 0.0) {
+    const int rc = choose_refine(b, b->dt, &b->n_refine);
+    if (rc) return rc;
+  }
+  return NPFEM_OK;
+}
+
 int factorise(npfem_batch_s* b, double dt) {
   int Nmax = 0;
   for (auto& c : b->cls) Nmax = std::max(Nmax, c.Npad);
@@ -437,30 +490,65 @@ int factorise(npfem_batch_s* b, double dt) {
   return NPFEM_OK;
 }
 
+#define NPFEM_TIMED(kind, expr, what)                           \
+  do {                                                          \
+    const bool t_ = (b->flags & NPFEM_OPT_KERNEL_TIMING) != 0;  \
+    const int idx_ = t_ ? b->ev_begin(st) : -1;                 \
+    HIP_TRY(expr, what);                                        \
+    if (idx_ >= 0) b->ev_end(idx_, kind, st);                   \
+  } while (0)
+
+// C = A_c^-1 B for one class: one GEMM with the stored class operator, then
+// the correction sweeps C += A_0^-1 (B - A_c C) (per-cell weights, low
+// precision). B and C are batch column buffers.
 template <typename T>
-int enqueue_step(npfem_batch_s* b, const T* forces, double h, int n_iter, hipStream_t st) {
-  T* pos = static_cast<T*>(b->pos);
-  T* vel = static_cast<T*>(b->vel);
-  T* delta = static_cast<T*>(b->delta);
-  T* cterm = static_cast<T*>(b->cterm);
-  T* rhs = static_cast<T*>(b->rhs);
+int enqueue_solve(npfem_batch_s* b, ClassState& c, T* B, T* C, double h, hipStream_t st) {
   T* res = static_cast<T*>(b->res);
   const T* w = b->per_cell ? static_cast<const T*>(b->weights_dev) : nullptr;
   const bool lp = b->gemm_kind >= 2;
   float* colmax = (b->gemm_kind == 3) ? b->colmax : nullptr;
-  const bool want_energy = (b->flags & NPFEM_OPT_ENERGY) != 0;
-  const bool timing = (b->flags & NPFEM_OPT_KERNEL_TIMING) != 0;
-#define NPFEM_TIMED(kind, expr, what)                   \
-  do {                                                  \
-    const int idx_ = timing ? b->ev_begin(st) : -1;     \
-    HIP_TRY(expr, what);                                \
-    if (idx_ >= 0) b->ev_end(idx_, kind, st);           \
-  } while (0)
-  if (timing && b->ev_used > 60000) HIP_TRY(b->ev_harvest(), "kernel timing");
+  GemmArgs g;
+  g.A = c.op;
+  g.B = B + c.elem0;
+  g.C = C + c.elem0;
+  g.colscale = colmax ? colmax + c.col0 : nullptr;
+  g.Npad = c.Npad;
+  g.ncols = 3 * c.n_cells;
+  g.mode = lp ? EPI_SPLIT_SET : EPI_SET;
+  g.hm = h * h / c.mat.vertex_mass;
+  g.beta = c.beta;
+  NPFEM_TIMED(NPFEM_KERNEL_GLOBAL, launch_gemm(b->gemm_kind, c.gemm_tile, g, st), "global step");
+  for (int s = 0; s < b->n_refine; ++s) {
+    NPFEM_TIMED(NPFEM_KERNEL_RESIDUAL,
+                launch_residual<T>(slice_of<T>(c), B, C, res, w, colmax, h, st), "residual");
+    GemmArgs r = g;
+    r.B = res + c.elem0;
+    r.mode = lp ? EPI_SPLIT_ADD : EPI_ADD;
+    NPFEM_TIMED(NPFEM_KERNEL_GLOBAL, launch_gemm(b->gemm_kind, c.gemm_tile, r, st), "refinement");
+  }
+  return NPFEM_OK;
+}
+
+// One time step of every cell on state (pos, vel). dslots, if given, holds
+// n_iter + 1 column buffers: iterate k is read from dslots[k] and the solve
+// writes dslots[k + 1] (recording every PD iterate for the adjoint);
+// otherwise all iterates share the batch's delta buffer.
+template <typename T>
+int enqueue_step(npfem_batch_s* b, T* pos, T* vel, const T* forces, double h, int n_iter,
+                 hipStream_t st, T* const* dslots = nullptr) {
+  T* delta = static_cast<T*>(b->delta);
+  T* cterm = static_cast<T*>(b->cterm);
+  T* rhs = static_cast<T*>(b->rhs);
+  const T* w = b->per_cell ? static_cast<const T*>(b->weights_dev) : nullptr;
+  float* colmax = (b->gemm_kind == 3) ? b->colmax : nullptr;
+  const bool want_energy = (b->flags & NPFEM_OPT_ENERGY) != 0 && !dslots;
+  auto slot = [&](int k) { return dslots ? dslots[k] : delta; };
+  if ((b->flags & NPFEM_OPT_KERNEL_TIMING) && b->ev_used > 60000)
+    HIP_TRY(b->ev_harvest(), "kernel timing");
   for (auto& c : b->cls) {
     if (c.n_cells == 0) continue;
     NPFEM_TIMED(NPFEM_KERNEL_PREDICT,
-                launch_predict<T>(slice_of<T>(c), pos, vel, forces, b->sumN, delta, cterm,
+                launch_predict<T>(slice_of<T>(c), pos, vel, forces, b->sumN, slot(0), cterm,
                                   b->status, h, st),
                 "predict");
   }
@@ -471,7 +559,7 @@ int enqueue_step(npfem_batch_s* b, const T* forces, double h, int n_iter, hipStr
       a.cs = slice_of<T>(c);
       a.pos = pos;
       a.sumN = b->sumN;
-      a.delta = delta;
+      a.delta = slot(it);
       a.cterm = cterm;
       a.rhs = rhs;
       a.weights = w;
@@ -486,42 +574,25 @@ int enqueue_step(npfem_batch_s* b, const T* forces, double h, int n_iter, hipStr
     }
     for (auto& c : b->cls) {
       if (c.n_cells == 0) continue;
-      GemmArgs g;
-      g.A = c.op;
-      g.B = rhs + c.elem0;
-      g.C = delta + c.elem0;
-      g.colscale = colmax ? colmax + c.col0 : nullptr;
-      g.Npad = c.Npad;
-      g.ncols = 3 * c.n_cells;
-      g.mode = lp ? EPI_SPLIT_SET : EPI_SET;
-      g.hm = h * h / c.mat.vertex_mass;
-      g.beta = c.beta;
-      NPFEM_TIMED(NPFEM_KERNEL_GLOBAL, launch_gemm(b->gemm_kind, c.gemm_tile, g, st),
-                  "global step");
-      for (int s = 0; s < b->n_refine; ++s) {
-        NPFEM_TIMED(NPFEM_KERNEL_RESIDUAL,
-                    launch_residual<T>(slice_of<T>(c), rhs, delta, res, w, colmax, h, st),
-                    "residual");
-        GemmArgs r = g;
-        r.B = res + c.elem0;
-        r.mode = lp ? EPI_SPLIT_ADD : EPI_ADD;
-        NPFEM_TIMED(NPFEM_KERNEL_GLOBAL, launch_gemm(b->gemm_kind, c.gemm_tile, r, st),
-                    "refinement");
-      }
+      const int rc = enqueue_solve<T>(b, c, rhs, slot(it + 1), h, st);
+      if (rc) return rc;
     }
   }
   for (auto& c : b->cls) {
     if (c.n_cells == 0) continue;
     NPFEM_TIMED(NPFEM_KERNEL_UPDATE,
-                launch_update<T>(slice_of<T>(c), pos, vel, b->sumN, delta, h, st), "update");
+                launch_update<T>(slice_of<T>(c), pos, vel, b->sumN, slot(n_iter), h, st),
+                "update");
   }
-#undef NPFEM_TIMED
   return NPFEM_OK;
 }
 
 int enqueue_any(npfem_batch_s* b, const void* forces, double h, int n_iter, hipStream_t st) {
-  if (b->fp64) return enqueue_step<double>(b, static_cast<const double*>(forces), h, n_iter, st);
-  return enqueue_step<float>(b, static_cast<const float*>(forces), h, n_iter, st);
+  if (b->fp64)
+    return enqueue_step<double>(b, static_cast<double*>(b->pos), static_cast<double*>(b->vel),
+                                static_cast<const double*>(forces), h, n_iter, st);
+  return enqueue_step<float>(b, static_cast<float*>(b->pos), static_cast<float*>(b->vel),
+                             static_cast<const float*>(forces), h, n_iter, st);
 }
 
 int prepare_kernels(npfem_batch_s* b) {
@@ -638,6 +709,127 @@ int autotune(npfem_batch_s* b, double h) {
   hipEventDestroy(e1);
   HIP_TRY(hipStreamSynchronize(st), "autotune");
   return rc;
+}
+
+int grow(void** p, size_t* have, size_t need, const char* what) {
+  if (*have >= need && *p) return NPFEM_OK;
+  if (*p) hipFree(*p);
+  *p = nullptr;
+  *have = 0;
+  hipError_t e = hipMalloc(p, std::max<size_t>(need, 16));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return hip_fail(e, what);
+  }
+  *have = need;
+  return NPFEM_OK;
+}
+
+// Reverse of the last rollout (see npfem_rollout_adjoint). Segment by
+// segment, backwards: recompute the segment from its checkpoint recording x_n
+// and every PD iterate, then reverse its steps and iterations.
+template <typename T>
+int adjoint_impl(npfem_batch_s* b, const void* dL_dx, const void* dL_dv, void* dL_dw, void* dL_df,
+                 void* dL_dx0, void* dL_dv0) {
+  hipStream_t st = b->stream;
+  const double h = b->ro_dt;
+  const int K = b->ro_iter, ce = b->ro_every, S = b->ro_steps;
+  const int n_seg = (S + ce - 1) / ce;
+  const size_t sv = 3 * (size_t)b->sumN, cols = (size_t)b->total_elems;
+  const size_t per_step = sv + (size_t)(K + 1) * cols;
+  int rc;
+  if ((rc = grow(&b->tape, &b->tape_bytes, sizeof(T) * per_step * ce, "adjoint tape"))) return rc;
+  const size_t wbytes = sizeof(double) * 4 * (size_t)b->n_cells;
+  if ((rc = grow(&b->adj_work, &b->adj_work_bytes, sizeof(T) * (4 * sv + 3 * cols) + wbytes + 256,
+                 "adjoint workspace")))
+    return rc;
+  double* wbar = static_cast<double*>(b->adj_work);
+  T* xs = reinterpret_cast<T*>(reinterpret_cast<char*>(b->adj_work) + ((wbytes + 255) / 256) * 256);
+  T* vs = xs + sv;
+  T* xbar = vs + sv;
+  T* vbar = xbar + sv;
+  T* lam = vbar + sv;
+  T* gbar = lam + cols;
+  T* sbar = gbar + cols;
+  T* tape = static_cast<T*>(b->tape);
+  T* ckpt = static_cast<T*>(b->ckpt);
+  T* fbar = static_cast<T*>(dL_df);
+  const T* forces = static_cast<const T*>(b->ro_forces);
+  const T* w = b->per_cell ? static_cast<const T*>(b->weights_dev) : nullptr;
+
+  for (auto& c : b->cls) {
+    hipError_t e = local_prepare<T>(slice_of<T>(c).cv, c.local_block);
+    if (e == hipSuccess) e = adjoint_prepare<T>(slice_of<T>(c).cv);
+    if (e != hipSuccess) return hip_fail(e, "adjoint kernel attributes");
+  }
+  HIP_TRY(hipMemcpyAsync(xbar, dL_dx, sizeof(T) * sv, hipMemcpyDeviceToDevice, st), "adjoint");
+  if (dL_dv)
+    HIP_TRY(hipMemcpyAsync(vbar, dL_dv, sizeof(T) * sv, hipMemcpyDeviceToDevice, st), "adjoint");
+  else
+    HIP_TRY(hipMemsetAsync(vbar, 0, sizeof(T) * sv, st), "adjoint");
+  HIP_TRY(hipMemsetAsync(wbar, 0, wbytes, st), "adjoint");
+  if (fbar) HIP_TRY(hipMemsetAsync(fbar, 0, sizeof(T) * sv, st), "adjoint");
+
+  std::vector<T*> slots(K + 1);
+  for (int seg = n_seg - 1; seg >= 0; --seg) {
+    const int s0 = seg * ce, ns = std::min(ce, S - s0);
+    HIP_TRY(hipMemcpyAsync(xs, ckpt + 2 * (size_t)seg * sv, sizeof(T) * sv,
+                           hipMemcpyDeviceToDevice, st), "recompute");
+    HIP_TRY(hipMemcpyAsync(vs, ckpt + (2 * (size_t)seg + 1) * sv, sizeof(T) * sv,
+                           hipMemcpyDeviceToDevice, st), "recompute");
+    for (int j = 0; j < ns; ++j) {
+      T* tj = tape + (size_t)j * per_step;
+      HIP_TRY(hipMemcpyAsync(tj, xs, sizeof(T) * sv, hipMemcpyDeviceToDevice, st), "recompute");
+      for (int k = 0; k <= K; ++k) slots[k] = tj + sv + (size_t)k * cols;
+      if ((rc = enqueue_step<T>(b, xs, vs, forces, h, K, st, slots.data()))) return rc;
+    }
+    for (int j = ns - 1; j >= 0; --j) {
+      T* tj = tape + (size_t)j * per_step;
+      for (int k = 0; k <= K; ++k) slots[k] = tj + sv + (size_t)k * cols;
+      for (auto& c : b->cls)
+        HIP_TRY(launch_adj_begin<T>(slice_of<T>(c), xbar, vbar, b->sumN, gbar, sbar, h, st),
+                "adjoint step");
+      for (int k = K - 1; k >= 0; --k) {
+        for (auto& c : b->cls) {
+          if (c.n_cells == 0) continue;
+          if ((rc = enqueue_solve<T>(b, c, gbar, lam, h, st))) return rc;
+          AdjArgs<T> a;
+          a.cs = slice_of<T>(c);
+          a.xn = tj;
+          a.sumN = b->sumN;
+          a.delta_k = slots[k];
+          a.delta_k1 = slots[k + 1];
+          a.lam = lam;
+          a.gbar = gbar;
+          a.sbar = sbar;
+          a.wbar = wbar;
+          a.weights = w;
+          a.status = b->status;
+          a.h = h;
+          a.m = c.mat.vertex_mass;
+          a.max_vol_iter = b->max_vol_iter;
+          LocalArgs<T> tol;
+          set_volume_tolerances(tol, c, b->fp64);
+          a.vol_tol = tol.vol_tol;
+          a.vol_abs = tol.vol_abs;
+          HIP_TRY(launch_adjoint_local<T>(a, st), "adjoint iteration");
+        }
+      }
+      for (auto& c : b->cls)
+        HIP_TRY(launch_adj_end<T>(slice_of<T>(c), xbar, vbar, b->sumN, gbar, sbar, fbar, h, st),
+                "adjoint step");
+    }
+  }
+  if (dL_dw)
+    HIP_TRY(hipMemcpyAsync(dL_dw, wbar, wbytes, hipMemcpyDeviceToDevice, st), "adjoint outputs");
+  if (dL_dx0)
+    HIP_TRY(hipMemcpyAsync(dL_dx0, xbar, sizeof(T) * sv, hipMemcpyDeviceToDevice, st),
+            "adjoint outputs");
+  if (dL_dv0)
+    HIP_TRY(hipMemcpyAsync(dL_dv0, vbar, sizeof(T) * sv, hipMemcpyDeviceToDevice, st),
+            "adjoint outputs");
+  HIP_TRY(hipStreamSynchronize(st), "adjoint");
+  return NPFEM_OK;
 }
 
 }  // namespace
@@ -768,30 +960,9 @@ int npfem_create_batch(const npfem_mesh* meshes, int32_t n_meshes, const int32_t
   b->total_cols = col;
   b->total_elems = elem;
 
-  // per-cell weights (kept on the device only when they differ from nominal)
-  b->weights_host.resize(4 * (size_t)n_cells);
-  for (int c = 0; c < n_cells; ++c) {
-    const npfem_material& m = b->cls[cell_mesh[c]].mat;
-    const double nom[4] = {m.w_stretch, m.w_area, m.w_bend, m.w_volume};
-    for (int i = 0; i < 4; ++i) {
-      const double w = cell_weights ? cell_weights[4 * (size_t)c + i] : nom[i];
-      b->weights_host[4 * (size_t)c + i] = w;
-      if (w != nom[i]) b->per_cell = true;
-    }
-  }
+  b->cell_class.assign(cell_mesh, cell_mesh + n_cells);
   int rc;
-  if (b->per_cell) {
-    if ((rc = dalloc(b.get(), &b->weights_dev, tsz * 4 * (size_t)n_cells, "weights"))) return rc;
-    hipError_t e;
-    if (b->fp64) {
-      e = hipMemcpy(b->weights_dev, b->weights_host.data(), 8 * 4 * (size_t)n_cells,
-                    hipMemcpyHostToDevice);
-    } else {
-      std::vector<float> wf(b->weights_host.begin(), b->weights_host.end());
-      e = hipMemcpy(b->weights_dev, wf.data(), 4 * 4 * (size_t)n_cells, hipMemcpyHostToDevice);
-    }
-    if (e != hipSuccess) return hip_fail(e, "weights upload");
-  }
+  if ((rc = apply_weights(b.get(), cell_weights))) return rc;
   const size_t colbytes = tsz * (size_t)b->total_elems;
   if ((rc = dalloc(b.get(), &b->delta, colbytes, "delta"))) return rc;
   if ((rc = dalloc(b.get(), &b->cterm, colbytes, "cterm"))) return rc;
@@ -863,6 +1034,77 @@ int npfem_step(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter)
   b->energy_iters = n_iter;
   if (b->flags & NPFEM_OPT_SYNC_CHECK) return npfem_sync_status(b);
   return NPFEM_OK;
+}
+
+int npfem_set_weights(npfem_batch b, const double* cell_weights) {
+  g_err.clear();
+  if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
+  if (cell_weights) {
+    for (long long i = 0; i < 4LL * b->n_cells; ++i)
+      if (!std::isfinite(cell_weights[i]) || cell_weights[i] < 0.0)
+        return fail(NPFEM_ERR_INVALID_ARG, "cell_weights must be finite and non-negative");
+  }
+  DeviceGuard guard(b->device);
+  HIP_TRY(hipStreamSynchronize(b->stream), "sync before weight update");
+  const int rc = apply_weights(b, cell_weights);
+  if (b->graph) {
+    hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  b->ro_valid = false;
+  return rc;
+}
+
+int npfem_rollout(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter,
+                  int32_t n_steps, int32_t ckpt_every) {
+  g_err.clear();
+  if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
+  if (n_steps < 1 || ckpt_every < 1 || ckpt_every > n_steps)
+    return fail(NPFEM_ERR_INVALID_ARG, "need n_steps >= 1 and 1 <= ckpt_every <= n_steps");
+  DeviceGuard guard(b->device);
+  const size_t tsz = b->fp64 ? sizeof(double) : sizeof(float);
+  const size_t sv = 3 * (size_t)b->sumN;
+  const int n_seg = (n_steps + ckpt_every - 1) / ckpt_every;
+  b->ro_valid = false;
+  if (b->ckpt_bytes < tsz * 2 * sv * n_seg) HIP_TRY(hipStreamSynchronize(b->stream), "sync");
+  int rc = grow(&b->ckpt, &b->ckpt_bytes, tsz * 2 * sv * n_seg, "checkpoints");
+  if (rc) return rc;
+  char* ck = static_cast<char*>(b->ckpt);
+  for (int s = 0; s < n_steps; ++s) {
+    if (s % ckpt_every == 0) {
+      const size_t seg = s / ckpt_every;
+      HIP_TRY(hipMemcpyAsync(ck + tsz * 2 * seg * sv, b->pos, tsz * sv, hipMemcpyDeviceToDevice,
+                             b->stream), "checkpoint");
+      HIP_TRY(hipMemcpyAsync(ck + tsz * (2 * seg + 1) * sv, b->vel, tsz * sv,
+                             hipMemcpyDeviceToDevice, b->stream), "checkpoint");
+    }
+    if ((rc = npfem_step(b, ext_forces, dt, n_iter))) return rc;
+  }
+  b->ro_steps = n_steps;
+  b->ro_iter = n_iter;
+  b->ro_every = ckpt_every;
+  b->ro_dt = dt;
+  b->ro_forces = ext_forces;
+  b->ro_valid = true;
+  return NPFEM_OK;
+}
+
+int npfem_rollout_adjoint(npfem_batch b, const void* dL_dx, const void* dL_dv, void* dL_dw,
+                          void* dL_df, void* dL_dx0, void* dL_dv0) {
+  g_err.clear();
+  if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
+  if (!dL_dx) return fail(NPFEM_ERR_INVALID_ARG, "dL_dx is NULL");
+  if (!b->ro_valid || b->dt != b->ro_dt)
+    return fail(NPFEM_ERR_INVALID_ARG,
+                "no rollout to reverse (run npfem_rollout; weights and dt must not change)");
+  if (b->gemm_kind == 3)
+    return fail(NPFEM_ERR_INVALID_ARG, "the adjoint supports FP64, FP32 and BF16 batches");
+  DeviceGuard guard(b->device);
+  HIP_TRY(hipStreamSynchronize(b->stream), "sync before adjoint");
+  const int rc = b->fp64 ? adjoint_impl<double>(b, dL_dx, dL_dv, dL_dw, dL_df, dL_dx0, dL_dv0)
+                         : adjoint_impl<float>(b, dL_dx, dL_dv, dL_dw, dL_df, dL_dx0, dL_dv0);
+  if (rc) return rc;
+  return npfem_sync_status(b);
 }
 
 int npfem_sync_status(npfem_batch b) {

@@ -74,6 +74,25 @@ struct LocalArgs {
   double vol_abs;      // absolute test: |d lam| |grad V|_2 below this (length units)
 };
 
+// Reverse of one PD iteration (kernels_adjoint.hip).
+template <typename T>
+struct AdjArgs {
+  ClassSlice<T> cs;
+  const T* xn;         // positions x_n of the step, SoA [3][sumN]
+  long long sumN;
+  const T* delta_k;    // q^k = x_n + delta_k (columns)
+  const T* delta_k1;   // q^{k+1}
+  const T* lam;        // A^-1 gbar(q^{k+1}) (columns)
+  T* gbar;             // out: dL/dq^k (columns)
+  T* sbar;             // accumulates (m/h^2) lam (columns)
+  double* wbar;        // [n_cells_total][4] accumulates dL/dw
+  const T* weights;    // [n_cells_total][4] or nullptr
+  int* status;
+  double h, m;
+  int max_vol_iter;
+  double vol_tol, vol_abs;
+};
+
 enum EpilogueMode : int { EPI_SET = 0, EPI_ADD = 1, EPI_SPLIT_SET = 2, EPI_SPLIT_ADD = 3 };
 
 struct GemmArgs {
@@ -110,6 +129,17 @@ hipError_t launch_residual(const ClassSlice<T>& cs, const T* rhs, const T* delta
 template <typename T>
 hipError_t launch_volume(const ClassSlice<T>& cs, const T* pos, long long sumN, double* out,
                          hipStream_t st);
+
+template <typename T>
+hipError_t adjoint_prepare(const ClassView<T>& cv);
+template <typename T>
+hipError_t launch_adjoint_local(const AdjArgs<T>& a, hipStream_t st);
+template <typename T>
+hipError_t launch_adj_begin(const ClassSlice<T>& cs, const T* xbar, const T* vbar, long long sumN,
+                            T* gbar, T* sbar, double h, hipStream_t st);
+template <typename T>
+hipError_t launch_adj_end(const ClassSlice<T>& cs, T* xbar, T* vbar, long long sumN,
+                          const T* gbar, const T* sbar, T* fbar, double h, hipStream_t st);
 
 // Global-step GEMM variants. kind: 0 = FP32, 1 = FP64, 2 = BF16, 3 = FP16.
 hipError_t launch_gemm(int kind, int tile, const GemmArgs& g, hipStream_t st);

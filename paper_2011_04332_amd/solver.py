@@ -135,6 +135,40 @@ class Batch:
     def sync_status(self):
         _lib.check(_lib.load().npfem_sync_status(self.handle))
 
+    def set_weights(self, cell_weights):
+        """Per-cell (stretch, area, bend, volume) weights [n_cells, 4]; None = nominal."""
+        w = None if cell_weights is None else np.ascontiguousarray(cell_weights, dtype=np.float64)
+        if w is not None and w.shape != (self.n_cells, 4):
+            raise ValueError("cell_weights must be [n_cells, 4]")
+        _lib.check(_lib.load().npfem_set_weights(self.handle, None if w is None else w.ctypes.data))
+
+    def rollout(self, forces: torch.Tensor, dt: float, n_iter: int, n_steps: int, ckpt_every: int):
+        """n_steps steps under constant forces, checkpointing every ckpt_every steps."""
+        self._check_field(forces, "forces")
+        self._forces = forces
+        _lib.check(_lib.load().npfem_rollout(self.handle, forces.data_ptr(), float(dt), int(n_iter),
+                                             int(n_steps), int(ckpt_every)))
+
+    def rollout_adjoint(self, dL_dx: torch.Tensor, dL_dv: torch.Tensor = None):
+        """Gradients of L(x_T, v_T) of the last rollout:
+        (dL/dw [n_cells, 4] float64, dL/dforces, dL/dx0, dL/dv0)."""
+        self._check_field(dL_dx, "dL_dx")
+        if dL_dv is not None:
+            self._check_field(dL_dv, "dL_dv")
+        dw = torch.zeros((self.n_cells, 4), dtype=torch.float64, device=self.pos.device)
+        df = torch.empty_like(self.pos)
+        dx0 = torch.empty_like(self.pos)
+        dv0 = torch.empty_like(self.pos)
+        _lib.check(_lib.load().npfem_rollout_adjoint(
+            self.handle, dL_dx.data_ptr(), None if dL_dv is None else dL_dv.data_ptr(),
+            dw.data_ptr(), df.data_ptr(), dx0.data_ptr(), dv0.data_ptr()))
+        return dw, df, dx0, dv0
+
+    def _check_field(self, t, name):
+        if not (t.is_cuda and t.dtype == self.dtype and t.is_contiguous()
+                and tuple(t.shape) == tuple(self.pos.shape)):
+            raise ValueError(f"{name} must match pos (contiguous CUDA, same dtype and shape)")
+
     def energy(self) -> np.ndarray:
         n_it = ctypes.c_int32()
         cap = 1000 * self.n_cells

@@ -1,0 +1,136 @@
+"""Hand-written adjoint (through the C ABI) against finite differences of the
+FP64 oracle and a closed form.
+
+Loss: L = sum |x_T - target|^2 with target the rest shape stretched 15 % along
+x at the cell's initial centroid. Gradients: per-cell weights (stretch, area,
+bend, volume) and constant external forces. Central differences use a step of
+1e-3 relative to each weight and 1e-3 on forces.
+
+Bounds: FP64 adjoint vs finite differences 1e-5 relative (the differences
+themselves are converged to ~1e-7 at that step); FP32 adjoint 1e-3 relative
+with an absolute floor of 1e-6 max|g| per cell, the bound proposed for the
+FP32 gradient (weight gradients depend on P - F(q'), which near rest is a
+small difference of O(1) FP32 quantities).
+"""
+import numpy as np
+import pytest
+
+from npfem_workload import suspensions as W
+from oracle import gradients as Gr
+
+from gpu_helpers import as_precision, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2011_04332_amd import _lib
+    _lib.load()
+
+
+def gpu_adjoint(s, precision, n_steps, n_iter, ckpt_every, target, weights=None):
+    import torch
+    from paper_2011_04332_amd import solver
+    b, pos, vel, f, meshes = solver.batch_from_suspension(s, precision=precision,
+                                                          per_cell_weights=weights is not None)
+    if weights is not None:
+        b.set_weights(weights)
+    b.rollout(f, s.dt, n_iter, n_steps, ckpt_every)
+    tgt = torch.tensor(target, dtype=pos.dtype, device=pos.device)
+    dldx = (2.0 * (pos - tgt)).contiguous()
+    dw, df, dx0, dv0 = b.rollout_adjoint(dldx)
+    out = (pos.double().cpu().numpy(), dw.cpu().numpy(), df.double().cpu().numpy(),
+           dx0.double().cpu().numpy(), dv0.double().cpu().numpy())
+    b.close()
+    return out
+
+
+def test_adjoint_free_flight_closed_form():
+    """Weights zero: x_T = x0 + T h v0 + h^2 T(T+1)/2 f/m, hence
+    dL/df = g h^2 T(T+1)/(2m), dL/dx0 = g, dL/dv0 = T h g with g = 2(x_T - target)."""
+    s = W.adjoint_rbcs(n_cells=3, n_steps=5, n_iter=3)
+    for mc in s.classes:
+        mc.weights = (0.0, 0.0, 0.0, 0.0)
+    s.weights[:] = 0.0
+    s.v0 = 0.1 * np.random.default_rng(1).standard_normal(s.v0.shape)
+    T, h, m = 5, s.dt, s.classes[0].mass
+    xT, dw, df, dx0, dv0 = gpu_adjoint(s, "fp64", T, 3, 2, s.extra["target"])
+    g = 2.0 * (xT - s.extra["target"])
+    assert np.allclose(df, g * h * h * T * (T + 1) / (2 * m), rtol=1e-12, atol=1e-14)
+    assert np.allclose(dx0, g, rtol=1e-12, atol=1e-14)
+    assert np.allclose(dv0, T * h * g, rtol=1e-12, atol=1e-14)
+
+
+def _fd_cell(s, c, n_steps, n_iter, comps):
+    mc, x0, v0, f, w = s.cell_arrays(c)
+    tgt = s.extra["target"][:, s.cell_slice(c)].T
+    gw = Gr.fd_weight_grad(mc, w, mc.mass, s.dt, x0, v0, f, tgt, n_iter, n_steps, h=1e-3)
+    gf = Gr.fd_force_grad(mc, w, mc.mass, s.dt, x0, v0, f, tgt, n_iter, n_steps, comps, h=1e-3)
+    return gw, gf
+
+
+def _check(gpu_w, gpu_f, fd_w, fd_f, comps, rtol, floor):
+    scale = max(np.abs(fd_w).max(), np.abs(fd_f).max())
+    for i in range(4):
+        assert abs(gpu_w[i] - fd_w[i]) <= rtol * abs(fd_w[i]) + floor * scale, (i, gpu_w, fd_w)
+    gf = np.array([gpu_f[v, d] for v, d in comps])
+    assert np.all(np.abs(gf - fd_f) <= rtol * np.abs(fd_f) + floor * scale), (gf, fd_f)
+
+
+def test_adjoint_fp64_stiff_per_cell_weights():
+    """FP64, stiff time step, per-cell weights (correction sweeps), 5 steps in
+    checkpoint segments of 2, 2 and 1."""
+    s = W.stiff(W.adjoint_rbcs(n_cells=3, n_steps=5, n_iter=4))
+    rng = np.random.default_rng(7)
+    s.weights = s.weights * rng.uniform(0.9, 1.1, size=s.weights.shape)
+    log("adjoint fp64 stiff")
+    xT, dw, df, dx0, dv0 = gpu_adjoint(s, "fp64", 5, 4, 2, s.extra["target"], weights=s.weights)
+    comps = [(0, 0), (311, 1), (640, 2)]
+    for c in (0, 2):
+        fd_w, fd_f = _fd_cell(s, c, 5, 4, comps)
+        sl = s.cell_slice(c)
+        log(f"cell {c}: gpu {dw[c]} fd {fd_w}")
+        _check(dw[c], df[:, sl].T, fd_w, fd_f, comps, 1e-5, 1e-9)
+
+
+@pytest.mark.parametrize("stiff", [False, True])
+def test_adjoint_fp32(stiff):
+    """FP32 at the adjoint workload's parameters (dt 1e-4) and its stiff twin;
+    64 cells on the GPU, 2 sampled cells against finite differences."""
+    n_steps, n_iter = (10, 10) if not stiff else (4, 5)
+    s = W.adjoint_rbcs(n_cells=64, n_steps=n_steps, n_iter=n_iter)
+    if stiff:
+        s = W.stiff(s)
+    s = as_precision(s, np.float32)
+    log(f"adjoint fp32 stiff={stiff}")
+    xT, dw, df, dx0, dv0 = gpu_adjoint(s, "fp32", n_steps, n_iter, 5 if not stiff else 2,
+                                       s.extra["target"])
+    comps = [(3, 0), (200, 2)]
+    for c in (5, 50):
+        fd_w, fd_f = _fd_cell(s, c, n_steps, n_iter, comps)
+        sl = s.cell_slice(c)
+        log(f"cell {c}: gpu {dw[c]} fd {fd_w}")
+        _check(dw[c], df[:, sl].T, fd_w, fd_f, comps, 1e-3, 1e-6)
+
+
+def test_autograd_function_matches_adjoint():
+    import torch
+    from paper_2011_04332_amd import autograd, solver
+    s = as_precision(W.stiff(W.adjoint_rbcs(n_cells=4, n_steps=3, n_iter=3)), np.float64)
+    b, pos, vel, f, _ = solver.batch_from_suspension(s, "fp64", per_cell_weights=True)
+    w = torch.tensor(s.weights, dtype=torch.float64, requires_grad=True)
+    ff = f.clone().requires_grad_(True)
+    x0 = pos.clone().requires_grad_(True)
+    v0 = vel.clone().requires_grad_(True)
+    tgt = torch.tensor(s.extra["target"], dtype=torch.float64, device=pos.device)
+    xT, vT = autograd.rollout(b, w, ff, x0, v0, s.dt, 3, 3, ckpt_every=1)
+    L = ((xT - tgt) ** 2).sum()
+    gw, gf, gx, gv = torch.autograd.grad(L, (w, ff, x0, v0))
+    dw, df, dx0, dv0 = b.rollout_adjoint((2 * (xT - tgt)).detach().contiguous())
+    assert torch.allclose(gw.cpu(), dw.cpu()) and torch.allclose(gf, df)
+    assert torch.allclose(gx, dx0) and torch.allclose(gv, dv0)
+    b.close()
