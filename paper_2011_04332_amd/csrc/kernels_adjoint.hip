@@ -17,6 +17,12 @@
 // volume correction per unit length, 1e-7..1e-4 at the solver's operating
 // points. Element VJPs go through LDS and are gathered per vertex in a fixed
 // order, as in the forward kernel.
+//
+// The weight-gradient residuals P_i(q) - S_i q' are formed in displacement
+// form, (P_i(q) - S_i q) + S_i (q - q') with q - q' = delta^k - delta^{k+1}
+// taken from the delta columns and the volume's P(q) - q = lam grad V taken
+// from the projection itself: near rest the residual is far smaller than the
+// positions, and q - q' evaluated from rounded positions would lose it.
 #include <algorithm>
 
 #include "device_utils.h"
@@ -64,8 +70,8 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
 
   double* red = smem_adj;  // 8 * NW doubles
   V4<T>* qs = reinterpret_cast<V4<T>*>(smem_adj + 8 * NW);  // q^k
-  V4<T>* q1s = qs + N;                                        // q^{k+1}
-  V4<T>* ls = q1s + N;                                        // lam, N + 1 records
+  V4<T>* dds = qs + N;                                        // q^k - q^{k+1}
+  V4<T>* ls = dds + N;                                        // lam, N + 1 records
   T* work = reinterpret_cast<T*>(ls + N + 1);
 
   T ws, wa, wb, wv;
@@ -86,7 +92,8 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
   for (int v = tid; v < N; v += BLOCK) {
     const T x0 = px[v], x1 = py[v], x2 = pz[v];
     qs[v] = V4<T>{x0 + d0[v], x1 + d0[Npad + v], x2 + d0[2 * Npad + v], T(0)};
-    q1s[v] = V4<T>{x0 + d1[v], x1 + d1[Npad + v], x2 + d1[2 * Npad + v], T(0)};
+    dds[v] = V4<T>{d0[v] - d1[v], d0[Npad + v] - d1[Npad + v], d0[2 * Npad + v] - d1[2 * Npad + v],
+                   T(0)};
     ls[v] = V4<T>{lcol[v], lcol[Npad + v], lcol[2 * Npad + v], T(0)};
   }
   if (tid == 0) ls[N] = V4<T>{T(0), T(0), T(0), T(0)};
@@ -141,8 +148,10 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
         }
         r[0] += (double)(g[j][0] * u[j][0] + g[j][1] * u[j][1] + g[j][2] * u[j][2]);
         r[1] += (double)(g[j][0] * w[j][0] + g[j][1] * w[j][1] + g[j][2] * w[j][2]);
-        const V4<T> p = ps[v], q1 = q1s[v];
-        wacc[3] += (double)(l.x * (p.x - q1.x) + l.y * (p.y - q1.y) + l.z * (p.z - q1.z));
+        // P_v(q) - q' = lam grad V + (q - q')
+        const V4<T> dq = dds[v];
+        wacc[3] += (double)(l.x * (mt * g[j][0] + dq.x) + l.y * (mt * g[j][1] + dq.y) +
+                            l.z * (mt * g[j][2] + dq.z));
       }
     }
     block_sum<2>(r, red);
@@ -165,17 +174,17 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
       const V4<T> r1 = reinterpret_cast<const V4<T>*>(cv.tri_rec)[2 * t + 1];
       const T g00 = r0.x, g01 = r0.y, g10 = r0.z, g11 = r0.w, g20 = r1.x, g21 = r1.y;
       const T area = r1.z;
-      T fq[3][2], f1[3][2], fl[3][2];
+      T fq[3][2], fd[3][2], fl[3][2];  // F(q), F(q - q'), F(lam)
       {
         const V4<T> qa = qs[id.x], qb = qs[id.y], qc = qs[id.z];
-        const V4<T> ua = q1s[id.x], ub = q1s[id.y], uc = q1s[id.z];
+        const V4<T> ua = dds[id.x], ub = dds[id.y], uc = dds[id.z];
         const V4<T> la = ls[id.x], lb = ls[id.y], lcc = ls[id.z];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
           fq[d][0] = comp(qa, d) * g00 + comp(qb, d) * g10 + comp(qc, d) * g20;
           fq[d][1] = comp(qa, d) * g01 + comp(qb, d) * g11 + comp(qc, d) * g21;
-          f1[d][0] = comp(ua, d) * g00 + comp(ub, d) * g10 + comp(uc, d) * g20;
-          f1[d][1] = comp(ua, d) * g01 + comp(ub, d) * g11 + comp(uc, d) * g21;
+          fd[d][0] = comp(ua, d) * g00 + comp(ub, d) * g10 + comp(uc, d) * g20;
+          fd[d][1] = comp(ua, d) * g01 + comp(ub, d) * g11 + comp(uc, d) * g21;
           fl[d][0] = comp(la, d) * g00 + comp(lb, d) * g10 + comp(lcc, d) * g20;
           fl[d][1] = comp(la, d) * g01 + comp(lb, d) * g11 + comp(lcc, d) * g21;
         }
@@ -188,8 +197,8 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
       for (int d = 0; d < 3; ++d) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-          es += fl[d][k] * (P.ps[d][k] - f1[d][k]);
-          ea += fl[d][k] * (P.pa[d][k] - f1[d][k]);
+          es += fl[d][k] * ((P.ps[d][k] - fq[d][k]) + fd[d][k]);
+          ea += fl[d][k] * ((P.pa[d][k] - fq[d][k]) + fd[d][k]);
           gs2[d][k] = ws * area * fl[d][k];
           ga2[d][k] = wa * area * fl[d][k];
           fb[d][k] = T(0);
@@ -237,13 +246,13 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
       const V4<T> r0 = reinterpret_cast<const V4<T>*>(cv.hin_rec)[2 * e];
       const V4<T> r1 = reinterpret_cast<const V4<T>*>(cv.hin_rec)[2 * e + 1];
       const T k0 = r0.x, k1 = r0.y, k2 = r0.z, k3 = r0.w, ce = r1.x, rr = r1.y;
-      T yq[3], y1[3], yl[3];
+      T yq[3], yd[3], yl[3];  // y(q), y(q - q'), y(lam)
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         yq[d] = k0 * comp(qs[id.x], d) + k1 * comp(qs[id.y], d) + k2 * comp(qs[id.z], d) +
                 k3 * comp(qs[id.w], d);
-        y1[d] = k0 * comp(q1s[id.x], d) + k1 * comp(q1s[id.y], d) + k2 * comp(q1s[id.z], d) +
-                k3 * comp(q1s[id.w], d);
+        yd[d] = k0 * comp(dds[id.x], d) + k1 * comp(dds[id.y], d) + k2 * comp(dds[id.z], d) +
+                k3 * comp(dds[id.w], d);
         yl[d] = k0 * comp(ls[id.x], d) + k1 * comp(ls[id.y], d) + k2 * comp(ls[id.z], d) +
                 k3 * comp(ls[id.w], d);
       }
@@ -252,7 +261,7 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
       const T sc = n2 > T(0) ? rr * in : T(1);
       T eb = T(0);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) eb += yl[d] * (sc * yq[d] - y1[d]);
+      for (int d = 0; d < 3; ++d) eb += yl[d] * ((sc - T(1)) * yq[d] + yd[d]);
       wacc[2] += (double)(ce * eb);
       // Pb = r y/|y|: Jacobian (r/|y|)(I - yh yh^T), symmetric
       const T wc = wb * ce;

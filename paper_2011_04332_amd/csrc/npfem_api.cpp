@@ -93,6 +93,10 @@ struct npfem_batch_s {
   int gemm_kind = 0;  // 0 FP32, 1 FP64, 2 BF16, 3 FP16
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
+  // per-class branch streams and fork/join events of the captured step
+  std::vector<hipStream_t> br_stream;
+  std::vector<hipEvent_t> br_join;
+  hipEvent_t br_fork = nullptr;
   uint32_t flags = 0;
   int n_refine_opt = -1;
   int max_vol_iter = 0;
@@ -171,8 +175,34 @@ struct npfem_batch_s {
     return hipSuccess;
   }
 
+  int ensure_branches() {
+    if (!br_fork) {
+      hipError_t e0 = hipEventCreateWithFlags(&br_fork, hipEventDisableTiming);
+      if (e0 != hipSuccess) {
+        br_fork = nullptr;
+        return hip_fail(e0, "branch events");
+      }
+    }
+    while (br_stream.size() < cls.size()) {
+      hipStream_t s = nullptr;
+      hipError_t er = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+      if (er != hipSuccess) return hip_fail(er, "branch streams");
+      br_stream.push_back(s);
+    }
+    while (br_join.size() < cls.size()) {
+      hipEvent_t e = nullptr;
+      hipError_t er = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+      if (er != hipSuccess) return hip_fail(er, "branch events");
+      br_join.push_back(e);
+    }
+    return NPFEM_OK;
+  }
+
   ~npfem_batch_s() {
     if (graph) hipGraphExecDestroy(graph);
+    for (hipStream_t s : br_stream) hipStreamDestroy(s);
+    for (hipEvent_t e : br_join) hipEventDestroy(e);
+    if (br_fork) hipEventDestroy(br_fork);
     for (hipEvent_t e : ev_pool) hipEventDestroy(e);
     for (auto& c : cls) {
       for (void* p : c.dev) hipFree(p);
@@ -529,13 +559,15 @@ int enqueue_solve(npfem_batch_s* b, ClassState& c, T* B, T* C, double h, hipStre
   return NPFEM_OK;
 }
 
-// One time step of every cell on state (pos, vel). dslots, if given, holds
+// One time step of the cells of class c on state (pos, vel): predict, n_iter
+// (local step, global solve) iterations, update. dslots, if given, holds
 // n_iter + 1 column buffers: iterate k is read from dslots[k] and the solve
 // writes dslots[k + 1] (recording every PD iterate for the adjoint);
-// otherwise all iterates share the batch's delta buffer.
+// otherwise all iterates share the batch's delta buffer. Classes touch
+// disjoint parts of every batch buffer, so their chains are independent.
 template <typename T>
-int enqueue_step(npfem_batch_s* b, T* pos, T* vel, const T* forces, double h, int n_iter,
-                 hipStream_t st, T* const* dslots = nullptr) {
+int enqueue_class_step(npfem_batch_s* b, ClassState& c, T* pos, T* vel, const T* forces,
+                       double h, int n_iter, hipStream_t st, T* const* dslots) {
   T* delta = static_cast<T*>(b->delta);
   T* cterm = static_cast<T*>(b->cterm);
   T* rhs = static_cast<T*>(b->rhs);
@@ -543,56 +575,79 @@ int enqueue_step(npfem_batch_s* b, T* pos, T* vel, const T* forces, double h, in
   float* colmax = (b->gemm_kind == 3) ? b->colmax : nullptr;
   const bool want_energy = (b->flags & NPFEM_OPT_ENERGY) != 0 && !dslots;
   auto slot = [&](int k) { return dslots ? dslots[k] : delta; };
+  NPFEM_TIMED(NPFEM_KERNEL_PREDICT,
+              launch_predict<T>(slice_of<T>(c), pos, vel, forces, b->sumN, slot(0), cterm,
+                                b->status, h, st),
+              "predict");
+  for (int it = 0; it < n_iter; ++it) {
+    LocalArgs<T> a;
+    a.cs = slice_of<T>(c);
+    a.pos = pos;
+    a.sumN = b->sumN;
+    a.delta = slot(it);
+    a.cterm = cterm;
+    a.rhs = rhs;
+    a.weights = w;
+    a.energy = want_energy ? b->energy + (size_t)it * b->n_cells : nullptr;
+    a.colmax = colmax;
+    a.status = b->status;
+    a.h = h;
+    a.m = c.mat.vertex_mass;
+    a.max_vol_iter = b->max_vol_iter;
+    set_volume_tolerances(a, c, b->fp64);
+    NPFEM_TIMED(NPFEM_KERNEL_LOCAL, launch_local<T>(a, c.local_block, st), "local step");
+    const int rc = enqueue_solve<T>(b, c, rhs, slot(it + 1), h, st);
+    if (rc) return rc;
+  }
+  NPFEM_TIMED(NPFEM_KERNEL_UPDATE,
+              launch_update<T>(slice_of<T>(c), pos, vel, b->sumN, slot(n_iter), h, st),
+              "update");
+  return NPFEM_OK;
+}
+
+// One time step of every cell. With fork set (graph capture of a batch of
+// several mesh classes) each class chain goes on a stream of its own that
+// forks from and joins back into st, so the captured graph holds one
+// parallel branch per class and small classes fill the CUs that a large
+// class leaves idle; otherwise the chains run one after the other on st.
+template <typename T>
+int enqueue_step(npfem_batch_s* b, T* pos, T* vel, const T* forces, double h, int n_iter,
+                 hipStream_t st, T* const* dslots = nullptr, bool fork = false) {
   if ((b->flags & NPFEM_OPT_KERNEL_TIMING) && b->ev_used > 60000)
     HIP_TRY(b->ev_harvest(), "kernel timing");
-  for (auto& c : b->cls) {
-    if (c.n_cells == 0) continue;
-    NPFEM_TIMED(NPFEM_KERNEL_PREDICT,
-                launch_predict<T>(slice_of<T>(c), pos, vel, forces, b->sumN, slot(0), cterm,
-                                  b->status, h, st),
-                "predict");
-  }
-  for (int it = 0; it < n_iter; ++it) {
+  int active = 0;
+  for (auto& c : b->cls) active += c.n_cells > 0;
+  if (!fork || active < 2) {
     for (auto& c : b->cls) {
       if (c.n_cells == 0) continue;
-      LocalArgs<T> a;
-      a.cs = slice_of<T>(c);
-      a.pos = pos;
-      a.sumN = b->sumN;
-      a.delta = slot(it);
-      a.cterm = cterm;
-      a.rhs = rhs;
-      a.weights = w;
-      a.energy = want_energy ? b->energy + (size_t)it * b->n_cells : nullptr;
-      a.colmax = colmax;
-      a.status = b->status;
-      a.h = h;
-      a.m = c.mat.vertex_mass;
-      a.max_vol_iter = b->max_vol_iter;
-      set_volume_tolerances(a, c, b->fp64);
-      NPFEM_TIMED(NPFEM_KERNEL_LOCAL, launch_local<T>(a, c.local_block, st), "local step");
-    }
-    for (auto& c : b->cls) {
-      if (c.n_cells == 0) continue;
-      const int rc = enqueue_solve<T>(b, c, rhs, slot(it + 1), h, st);
+      const int rc = enqueue_class_step<T>(b, c, pos, vel, forces, h, n_iter, st, dslots);
       if (rc) return rc;
     }
+    return NPFEM_OK;
   }
-  for (auto& c : b->cls) {
+  int rc = b->ensure_branches();
+  if (rc) return rc;
+  HIP_TRY(hipEventRecord(b->br_fork, st), "fork event");
+  for (size_t k = 0; k < b->cls.size(); ++k) {
+    ClassState& c = b->cls[k];
     if (c.n_cells == 0) continue;
-    NPFEM_TIMED(NPFEM_KERNEL_UPDATE,
-                launch_update<T>(slice_of<T>(c), pos, vel, b->sumN, slot(n_iter), h, st),
-                "update");
+    hipStream_t s = b->br_stream[k];
+    HIP_TRY(hipStreamWaitEvent(s, b->br_fork, 0), "fork wait");
+    rc = enqueue_class_step<T>(b, c, pos, vel, forces, h, n_iter, s, dslots);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(b->br_join[k], s), "join event");
+    HIP_TRY(hipStreamWaitEvent(st, b->br_join[k], 0), "join wait");
   }
   return NPFEM_OK;
 }
 
-int enqueue_any(npfem_batch_s* b, const void* forces, double h, int n_iter, hipStream_t st) {
+int enqueue_any(npfem_batch_s* b, const void* forces, double h, int n_iter, hipStream_t st,
+                bool fork = false) {
   if (b->fp64)
     return enqueue_step<double>(b, static_cast<double*>(b->pos), static_cast<double*>(b->vel),
-                                static_cast<const double*>(forces), h, n_iter, st);
+                                static_cast<const double*>(forces), h, n_iter, st, nullptr, fork);
   return enqueue_step<float>(b, static_cast<float*>(b->pos), static_cast<float*>(b->vel),
-                             static_cast<const float*>(forces), h, n_iter, st);
+                             static_cast<const float*>(forces), h, n_iter, st, nullptr, fork);
 }
 
 int prepare_kernels(npfem_batch_s* b) {
@@ -612,7 +667,7 @@ int capture_graph(npfem_batch_s* b, const void* forces, double h, int n_iter) {
   int rc = prepare_kernels(b);
   if (rc) return rc;
   HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-  rc = enqueue_any(b, forces, h, n_iter, b->cap_stream);
+  rc = enqueue_any(b, forces, h, n_iter, b->cap_stream, true);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
   if (rc) {
