@@ -10,6 +10,10 @@ Prints ONE JSON line: cell-PD-iterations per second over K timed steps
 dominant kernel (per-kernel HIP events in a second, eagerly launched pass over
 the same steps), the FP64 oracle timed on host cores on a bounded sample of
 cells, and the relative position error of those cells against the oracle.
+Beside it: the same workload with the global step in FP16 MFMA plus
+correction sweeps (throughput, speedup, error against the same oracle
+cells), and the forward + backward time of the differentiation workload
+(1024 RBCs, 50 steps x 10 iterations, checkpoints every 10 steps).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rbc_lattice]
 """
@@ -112,7 +116,7 @@ def gemm_flops(s):
 # gathers (12 per triangle corner, 24 per hinge) and the final sum.
 TRI_FLOPS, HINGE_FLOPS = 251, 60
 VOL_TRI_FLOPS, VOL_VERT_FLOPS = 36, 33
-VOLUME_PASSES = 2  # the minimum the settling test needs
+VOLUME_PASSES = 1  # the minimum: the settling test can stop after the first pass
 
 
 def local_flops(s):
@@ -170,6 +174,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--compare-precision", default="fp16", choices=["none", "bf16", "fp16"],
+                    help="also time the workload with this 16-bit global step (FP32 runs only)")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the forward + backward timing of the differentiation workload")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times), the "
                          "reference for scaling FETCH_SIZE / WRITE_SIZE counters")
@@ -244,20 +252,26 @@ def main():
         bt.close()
         traffic = measured_traffic(a.workload, a.precision)
         entries = {}
+        sweeps = configs[0][3]
         for kind in ("local", "global"):
             ms, n = kt[kind]
             avg_s = ms / n * 1e-3
+            # algorithmic work of all launches of this kind in the timing pass,
+            # spread evenly over the launches (classes differ in size)
             if kind == "local":
-                work = local_flops(s)
+                total = local_flops(s) * n_iter * a.steps
                 peak = PEAK["fp64_matrix_TF"] if a.precision == "fp64" else PEAK["fp32_vector_TF"]
                 e = {"bound": "alu", "kernel": "local_kernel (projections + RHS gather)",
-                     "algorithmic_flops": work, "algorithmic_hbm_bytes": local_bytes(s),
+                     "algorithmic_flops": total / n,
+                     "algorithmic_hbm_bytes": local_bytes(s, 8 if a.precision == "fp64" else 4)
+                     * n_iter * a.steps / n,
                      "alu_peak_without_packed_fp32": 78.6}
             else:
-                work = gemm_flops(s)
+                total = gemm_flops(s) * (1 + sweeps) * n_iter * a.steps
                 peak = PEAK[f"{a.precision}_matrix_TF"]
-                e = {"bound": "mfma", "kernel": "gemm_kernel (global step)", "algorithmic_flops": work}
-            achieved = work / avg_s / 1e12
+                e = {"bound": "mfma", "kernel": "gemm_kernel (global step)",
+                     "algorithmic_flops": total / n}
+            achieved = total / (ms * 1e-3) / 1e12
             e.update({"achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                       "frac": round(achieved / peak, 4), "avg_launch_us": round(avg_s * 1e6, 2),
                       "launches": n,
@@ -274,6 +288,68 @@ def main():
         print(f"[bench] kernel times (ms/step): {roof['kernel_ms_per_step']}", file=sys.stderr,
               flush=True)
 
+    # the same workload with a 16-bit global step plus correction sweeps
+    mixed, snap_m = None, None
+    if a.precision == "fp32" and a.compare_precision != "none":
+        pos.copy_(x_init)
+        vel.copy_(v_init)
+        bm = solver.Batch(meshes, s.cell_class, pos, vel,
+                          cell_weights=None if s.uniform_weights() else s.weights,
+                          precision=a.compare_precision, autotune=not a.no_autotune)
+        for _ in range(cpu_steps):
+            bm.step(f, dt, n_iter)
+        bm.sync_status()
+        snap_m = pos.double().cpu().numpy()
+        cfg_m = [bm.config(k) for k in range(len(s.classes))]
+        pos.copy_(x_init)
+        vel.copy_(v_init)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            bm.step(f, dt, n_iter)
+        torch.cuda.synchronize()
+        el_m = time.perf_counter() - t0
+        bm.sync_status()
+        bm.close()
+        mixed = {"precision": a.compare_precision, "dtype": DTYPE[a.compare_precision],
+                 "value": round(cell_its / el_m, 1), "ms_per_step": round(el_m / a.steps * 1e3, 4),
+                 "speedup_vs_fp32": round(elapsed / el_m, 4),
+                 "sweeps": cfg_m[0][3], "gemm_tiles": [[c[1], c[2]] for c in cfg_m]}
+        print(f"[bench] {a.compare_precision}: {mixed}", file=sys.stderr, flush=True)
+
+    # forward + backward of the differentiation workload
+    fwd_bwd = None
+    if not a.no_adjoint and a.precision in ("fp32", "fp64"):
+        sa = round_inputs(W.adjoint_rbcs(), a.precision)
+        ba, pa, va, fa, _ = solver.batch_from_suspension(sa, precision=a.precision)
+        tgt = torch.tensor(sa.extra["target"], dtype=pa.dtype, device=pa.device)
+        x0a, v0a = pa.clone(), va.clone()
+        n_st, n_it, every = sa.n_steps, sa.n_iter, sa.extra["ckpt_every"]
+
+        def fwd_bwd_once():
+            pa.copy_(x0a)
+            va.copy_(v0a)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ba.rollout(fa, sa.dt, n_it, n_st, every)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ba.rollout_adjoint((2.0 * (pa - tgt)).contiguous())
+            torch.cuda.synchronize()
+            return t1 - t0, time.perf_counter() - t1
+
+        fwd_bwd_once()  # graphs, checkpoint and tape buffers
+        tf, tb = fwd_bwd_once()
+        ba.sync_status()
+        ba.close()
+        fwd_bwd = {"workload": f"{sa.n_cells} RBC x 642 vertices, {n_st} steps x {n_it} PD "
+                               f"iterations, checkpoints every {every} steps, "
+                               "loss sum |x_T - target|^2",
+                   "forward_ms": round(tf * 1e3, 3), "backward_ms": round(tb * 1e3, 3),
+                   "fwd_bwd_ms": round((tf + tb) * 1e3, 3),
+                   "backward_over_forward": round(tb / tf, 3)}
+        print(f"[bench] forward+backward: {fwd_bwd}", file=sys.stderr, flush=True)
+
     cpu, parity = None, None
     if not a.no_cpu_baseline and snap is not None:
         ncores = min(a.cpu_cells, os.cpu_count() or 1, 16)
@@ -288,6 +364,9 @@ def main():
         errs = [S.rel_position_error(snap[:, s.cell_slice(c)].T, x) for c, x in ref.items()]
         parity = {"max_rel_pos_err": float(max(errs)), "cells": [int(c) for c in cells],
                   "steps": cpu_steps, "bound": 1e-6 if a.precision == "fp32" else 1e-5}
+        if mixed is not None and snap_m is not None:
+            mixed["max_rel_pos_err"] = float(max(
+                S.rel_position_error(snap_m[:, s.cell_slice(c)].T, x) for c, x in ref.items()))
         print(f"[bench] oracle: {cpu['value']} cell-it/s on {ncores} cores; parity {parity}",
               file=sys.stderr, flush=True)
 
@@ -311,6 +390,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity": parity,
+        "mixed_precision": mixed,
+        "fwd_bwd": fwd_bwd,
     }
     print(json.dumps(out), flush=True)
     b.close()

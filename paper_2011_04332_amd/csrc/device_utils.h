@@ -45,6 +45,72 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
   }
 }
 
+// Row shift of a double across the lanes of a 16-lane row (DPP row_shr:n);
+// lanes whose source lies before the row start read 0.
+template <int N>
+__device__ __forceinline__ double dpp_row_shr(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x110 | N, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x110 | N, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Wave-wide sum: inclusive scans of each 16-lane row (shifts 1, 2, 4, 8),
+// then the four row totals (lanes 15, 31, 47, 63) in a fixed order. Every
+// lane receives the same value; the order does not depend on the data.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_row_shr<1>(v);
+  v += dpp_row_shr<2>(v);
+  v += dpp_row_shr<4>(v);
+  v += dpp_row_shr<8>(v);
+  return (read_lane(v, 15) + read_lane(v, 31)) + (read_lane(v, 47) + read_lane(v, 63));
+}
+
+__device__ __forceinline__ double wave_max_dpp(double v) {
+  v = fmax(v, dpp_row_shr<1>(v));
+  v = fmax(v, dpp_row_shr<2>(v));
+  v = fmax(v, dpp_row_shr<4>(v));
+  v = fmax(v, dpp_row_shr<8>(v));
+  return fmax(fmax(read_lane(v, 15), read_lane(v, 31)), fmax(read_lane(v, 47), read_lane(v, 63)));
+}
+
+// Workgroup sums of NS doubles and, if WITH_MAX, the maximum of one more,
+// with a single barrier. red holds 2 * (NS + 1) * (blockDim.x / 64) doubles
+// and is used as two halves: consecutive calls must alternate buf (0, 1), so
+// that a call never overwrites the half that the previous call is still
+// reading. Identical totals in every thread. Call from uniform control flow.
+// The max input must be >= 0 (lanes with no data contribute 0).
+template <int NS, bool WITH_MAX>
+__device__ __forceinline__ void block_sum_max(double (&v)[NS], double& mx, double* red, int buf) {
+  constexpr int NV = NS + (WITH_MAX ? 1 : 0);
+  const int nw = blockDim.x / kWave;
+  const int w = threadIdx.x / kWave;
+  const int l = threadIdx.x % kWave;
+  double* r = red + (size_t)buf * (NS + 1) * nw;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) v[i] = wave_sum_dpp(v[i]);
+  if (WITH_MAX) mx = wave_max_dpp(mx);
+  if (l == 0) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) r[w * NV + i] = v[i];
+    if (WITH_MAX) r[w * NV + NS] = mx;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NS; ++i) v[i] = 0.0;
+  if (WITH_MAX) mx = 0.0;
+  for (int k = 0; k < nw; ++k) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) v[i] += r[k * NV + i];
+    if (WITH_MAX) mx = fmax(mx, r[k * NV + NS]);
+  }
+}
+
 __device__ __forceinline__ float block_max(float v, float* red) {
   const int nw = blockDim.x / kWave;
   const int w = threadIdx.x / kWave;

@@ -95,25 +95,29 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
   for (int j = 0; j < VPT; ++j) acc[j][0] = acc[j][1] = acc[j][2] = T(0);
 
   // ---- volume: closest point of q on {V(p) = V_rest} (local_common.h) ----
+  // (ps is scratch inside the projection; no thread reads it after the
+  // projection's last barrier, so the triangle chunks may overwrite it)
   {
     V4<T>* ps = reinterpret_cast<V4<T>*>(work);
-    T g[VPT][3];
-    volume_project<T, BLOCK, VPT>(cv, qs, ps, red, g, a.max_vol_iter, a.vol_tol, a.vol_abs, bad);
+    T g[VPT][3], p[VPT][3];
+    volume_project<T, BLOCK, VPT, false>(cv, qs, ps, red, g, p, a.max_vol_iter, a.vol_tol,
+                                         a.vol_abs, bad);
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
       if (v < N) {
-        const V4<T> p = ps[v], x = xs[v], q = qs[v];
-        acc[j][0] += wv * (p.x - x.x);
-        acc[j][1] += wv * (p.y - x.y);
-        acc[j][2] += wv * (p.z - x.z);
+        const V4<T> x = xs[v];
+        acc[j][0] += wv * (p[j][0] - x.x);
+        acc[j][1] += wv * (p[j][1] - x.y);
+        acc[j][2] += wv * (p[j][2] - x.z);
         if (want_energy) {
-          const double d0 = (double)q.x - p.x, d1 = (double)q.y - p.y, d2 = (double)q.z - p.z;
+          const V4<T> q = qs[v];
+          const double d0 = (double)q.x - p[j][0], d1 = (double)q.y - p[j][1],
+                       d2 = (double)q.z - p[j][2];
           e_acc += 0.5 * (double)wv * (d0 * d0 + d1 * d1 + d2 * d2);
         }
       }
     }
-    __syncthreads();
   }
 
   // ---- triangles: strain + area ----
@@ -198,6 +202,16 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
     __syncthreads();
   }
 
+  // inertia term of the own vertices, loaded here so that the loads are in
+  // flight during the hinge phase (barriers wait for LDS only)
+  T ct[VPT][3];
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    const int v = tid + j * BLOCK;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ct[j][d] = v < N ? ccol[d * Npad + v] : T(0);
+  }
+
   // ---- hinges: bending ----
   for (int base = 0; base < E; base += L.hch) {
     const int ne = min(L.hch, E - base);
@@ -279,11 +293,11 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
       for (int d = 0; d < 3; ++d) {
         T r = T(0);
         if (v < N) {
-          const T ct = ccol[d * Npad + v];
-          r = ct + acc[j < VPT ? j : VPT - 1][d];
+          const T c = ct[j < VPT ? j : VPT - 1][d];
+          r = c + acc[j < VPT ? j : VPT - 1][d];
           if (want_energy) {
             // (m/2h^2) |q - s|^2 with q - s = delta - (h^2/m) cterm
-            const double dd = (double)dcol[d * Npad + v] - hm * (double)ct;
+            const double dd = (double)dcol[d * Npad + v] - hm * (double)c;
             e_acc += 0.5 * (a.m / (a.h * a.h)) * dd * dd;
           }
         }

@@ -66,8 +66,10 @@ __global__ void __launch_bounds__(256) update_kernel(ClassSlice<T> cs, T* __rest
 }
 
 // Refinement residual res = r - A_c delta for each cell, with the per-cell
-// system A_c = (m/h^2 + w_v) I + (w_s + w_a) L_tri + w_b L_bend (sparse rows
-// of the two Laplacians). Products accumulate in FP64.
+// system A_c = (m/h^2 + w_v) I + (w_s + w_a) L_tri + w_b L_bend (fixed-width
+// rows of the two Laplacians). The cell's delta is staged in LDS (three
+// arrays of N + 1 values, the last one 0 for padding entries); products
+// accumulate in FP64. One workgroup per cell.
 template <typename T>
 __global__ void __launch_bounds__(256) residual_kernel(ClassSlice<T> cs, const T* __restrict__ rhs,
                                                        const T* __restrict__ delta,
@@ -76,13 +78,21 @@ __global__ void __launch_bounds__(256) residual_kernel(ClassSlice<T> cs, const T
                                                        float* __restrict__ colmax, double h) {
   extern __shared__ double smem_res[];
   float* redf = reinterpret_cast<float*>(smem_res);  // 4 floats
-  T* sd = reinterpret_cast<T*>(smem_res + 2);
+  T* sd = reinterpret_cast<T*>(smem_res + 2);        // [3][N + 1]
   const int lc = blockIdx.x;
-  const int N = cs.cv.N, Npad = cs.cv.Npad;
+  const int N = cs.cv.N, Npad = cs.cv.Npad, DL = cs.cv.DL;
   const long long cb = cs.elem0 + 3LL * lc * Npad;
-  for (int i = threadIdx.x; i < 3 * N; i += blockDim.x) {
-    const int d = i / N, v = i - d * N;
-    sd[i] = delta[cb + d * Npad + v];
+  const int* __restrict__ lcol = cs.cv.lap_col;
+  const T* __restrict__ lt = cs.cv.lap_t;
+  const T* __restrict__ lb = cs.cv.lap_b;
+  T* sx = sd;
+  T* sy = sd + (N + 1);
+  T* sz = sd + 2 * (N + 1);
+  for (int v = threadIdx.x; v <= N; v += blockDim.x) {
+    const bool in = v < N;
+    sx[v] = in ? delta[cb + v] : T(0);
+    sy[v] = in ? delta[cb + Npad + v] : T(0);
+    sz[v] = in ? delta[cb + 2 * Npad + v] : T(0);
   }
   __syncthreads();
   const int cell = cs.cell0 + lc;
@@ -95,19 +105,22 @@ __global__ void __launch_bounds__(256) residual_kernel(ClassSlice<T> cs, const T
   for (int v = threadIdx.x; v < Npad; v += blockDim.x) {
     double a0 = 0, a1 = 0, a2 = 0;
     if (v < N) {
-      a0 = diag * (double)sd[v];
-      a1 = diag * (double)sd[N + v];
-      a2 = diag * (double)sd[2 * N + v];
-      for (int e = cs.cv.lap_ptr[v]; e < cs.cv.lap_ptr[v + 1]; ++e) {
-        const int j = cs.cv.lap_col[e];
-        const double c = wt * (double)cs.cv.lap_t[e] + wb * (double)cs.cv.lap_b[e];
-        a0 += c * (double)sd[j];
-        a1 += c * (double)sd[N + j];
-        a2 += c * (double)sd[2 * N + j];
+      const T r0 = rhs[cb + v], r1 = rhs[cb + Npad + v], r2 = rhs[cb + 2 * Npad + v];
+      a0 = diag * (double)sx[v];
+      a1 = diag * (double)sy[v];
+      a2 = diag * (double)sz[v];
+#pragma unroll 4
+      for (int k = 0; k < DL; ++k) {
+        const int e = k * N + v;
+        const int j = lcol[e];
+        const double c = wt * (double)lt[e] + wb * (double)lb[e];
+        a0 += c * (double)sx[j];
+        a1 += c * (double)sy[j];
+        a2 += c * (double)sz[j];
       }
-      a0 = (double)rhs[cb + v] - a0;
-      a1 = (double)rhs[cb + Npad + v] - a1;
-      a2 = (double)rhs[cb + 2 * Npad + v] - a2;
+      a0 = (double)r0 - a0;
+      a1 = (double)r1 - a1;
+      a2 = (double)r2 - a2;
     }
     res[cb + v] = T(a0);
     res[cb + Npad + v] = T(a1);
@@ -173,7 +186,7 @@ template <typename T>
 hipError_t launch_residual(const ClassSlice<T>& cs, const T* rhs, const T* delta, T* res,
                            const T* weights, float* colmax, double h, hipStream_t st) {
   if (cs.n_cells == 0) return hipSuccess;
-  const size_t smem = 2 * sizeof(double) + sizeof(T) * 3 * (size_t)cs.cv.N;
+  const size_t smem = 2 * sizeof(double) + sizeof(T) * 3 * ((size_t)cs.cv.N + 1);
   hipLaunchKernelGGL(residual_kernel<T>, dim3(cs.n_cells), dim3(256), smem, st, cs, rhs, delta,
                      res, weights, colmax, h);
   return hipGetLastError();

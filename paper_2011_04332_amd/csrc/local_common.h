@@ -46,41 +46,56 @@ __device__ __forceinline__ void volume_gradient(const ClassView<T>& cv, const V4
 
 // Volume projection by the fixed-point map
 //   p <- q + lam grad V(p),  lam = (V_rest - V(p) - grad V(p).(q - p)) / |grad V(p)|^2,
-// with V(p) = (1/3) sum_v p_v . grad_v V(p) (Euler: V is cubic); per-vertex
-// dot products in T, sums over the cell in FP64. Stops when the last change
-// of lam moves the cell by less than vol_tol of the correction itself or
-// than vol_abs absolutely (|dp|_2 = |d lam| |grad V|_2). On return ps[0..N)
-// holds p, ps[N] = 0, g the gradient at the last iterate that produced p, and
-// the value is lam. Call from uniform control flow (contains barriers).
-template <typename T, int BLOCK, int VPT>
+// starting from p = q, with V(p) = (1/3) sum_v p_v . grad_v V(p) (Euler: V is
+// cubic); per-vertex dot products in T, sums over the cell in FP64.
+//
+// Stopping. After an iteration that is not the first, stop when the change
+// of lam moved the cell by less than vol_tol of the correction itself or than
+// vol_abs absolutely (|dp|_2 = |d lam| |grad V|_2). After the first, the next
+// change is predicted instead: to first order in lam the second iterate
+// moves by (3/2) lam^2 |g^T H g| / |g| along g plus lam^2 |H g| (H the
+// Hessian of V, g its gradient at q), at most (5/2) lam^2 |H| |g|, and
+// |g^T H g| <= |H| |g|^2 with |H| <= (DT / 3) max_v |q_v| (each block H_vw is
+// a sum of two cross-product matrices (1/6)[q_u]x, and g^T H g does not
+// change under translation). The test takes twice that bound.
+//
+// On return pv holds p for this thread's vertices, g the gradient that
+// produced p (p = q + lam g), and the value is lam. With STORE_P, ps[0..N)
+// also holds p and ps[N] = 0, behind a barrier. Without it, ps is scratch
+// (written only when a second iteration runs) and no thread reads it any
+// more. red: 8 * (BLOCK / 64) doubles. Call from uniform control flow.
+template <typename T, int BLOCK, int VPT, bool STORE_P>
 __device__ double volume_project(const ClassView<T>& cv, const V4<T>* qs, V4<T>* ps, double* red,
-                                 T (&g)[VPT][3], int max_it, double vol_tol, double vol_abs,
-                                 int& bad) {
+                                 T (&g)[VPT][3], T (&pv)[VPT][3], int max_it, double vol_tol,
+                                 double vol_abs, int& bad) {
   const int N = cv.N, tid = threadIdx.x;
-  for (int v = tid; v < N; v += BLOCK) ps[v] = qs[v];
-  if (tid == 0) ps[N] = V4<T>{T(0), T(0), T(0), T(0)};
-  __syncthreads();
+  const V4<T>* src = qs;  // current iterate p
   double lam = 0.0;
+  bool stored = false;
   for (int it = 0; it < max_it; ++it) {
     double s[3] = {0.0, 0.0, 0.0};
+    double mq = 0.0;
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
       g[j][0] = g[j][1] = g[j][2] = T(0);
       if (v < N) {
         T gx, gy, gz;
-        volume_gradient(cv, ps, v, gx, gy, gz);
+        volume_gradient(cv, src, v, gx, gy, gz);
         g[j][0] = gx;
         g[j][1] = gy;
         g[j][2] = gz;
-        const V4<T> p = ps[v];
+        const V4<T> p = src[v];
         const V4<T> q = qs[v];
         s[0] += (double)(p.x * gx + p.y * gy + p.z * gz);
         s[1] += (double)(gx * gx + gy * gy + gz * gz);
-        s[2] += (double)(gx * (q.x - p.x) + gy * (q.y - p.y) + gz * (q.z - p.z));
+        if (it > 0) s[2] += (double)(gx * (q.x - p.x) + gy * (q.y - p.y) + gz * (q.z - p.z));
+        else mq = fmax(mq, (double)(q.x * q.x + q.y * q.y + q.z * q.z));
       }
     }
-    block_sum<3>(s, red);  // barrier: all reads of ps are done
+    // one barrier; afterwards every read of src in this iteration is done
+    if (it == 0) block_sum_max<3, true>(s, mq, red, 0);
+    else block_sum_max<3, false>(s, mq, red, it & 1);
     double lam_new = (cv.vol_rest - s[0] / 3.0 - s[2]) / s[1];
     if (!isfinite(lam_new)) {
       bad = 1;
@@ -90,21 +105,34 @@ __device__ double volume_project(const ClassView<T>& cv, const V4<T>* qs, V4<T>*
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
-      if (v < N) {
-        const V4<T> q = qs[v];
-        V4<T> p;
-        p.x = q.x + lt * g[j][0];
-        p.y = q.y + lt * g[j][1];
-        p.z = q.z + lt * g[j][2];
-        p.w = T(0);
-        ps[v] = p;
-      }
+      const V4<T> q = v < N ? qs[v] : V4<T>{T(0), T(0), T(0), T(0)};
+      pv[j][0] = q.x + lt * g[j][0];
+      pv[j][1] = q.y + lt * g[j][1];
+      pv[j][2] = q.z + lt * g[j][2];
     }
-    __syncthreads();
     const double gn = sqrt(s[1]);
-    const bool conv = fabs(lam_new - lam) * gn <= fmax(vol_tol * fabs(lam_new) * gn, vol_abs);
+    const double allow = fmax(vol_tol * fabs(lam_new) * gn, vol_abs);
+    bool conv;
+    if (it == 0) {
+      const double hb = (double)cv.DT / 3.0 * sqrt(mq);
+      conv = 5.0 * lam_new * lam_new * hb * gn <= allow;
+    } else {
+      conv = fabs(lam_new - lam) * gn <= allow;
+    }
     lam = lam_new;
-    if (conv) break;
+    const bool last = conv || it + 1 == max_it;
+    if (last && !STORE_P) break;
+    // publish p for the next iteration's gradient (or for the caller)
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const int v = tid + j * BLOCK;
+      if (v < N) ps[v] = V4<T>{pv[j][0], pv[j][1], pv[j][2], T(0)};
+    }
+    if (!stored && tid == 0) ps[N] = V4<T>{T(0), T(0), T(0), T(0)};
+    stored = true;
+    __syncthreads();
+    src = ps;
+    if (last) break;
   }
   return lam;
 }

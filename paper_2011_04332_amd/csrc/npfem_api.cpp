@@ -78,9 +78,10 @@ struct ClassState {
   void* view_ptrs[19] = {};    // device pointers (see upload_class)
   void* op = nullptr;          // stored global-step operator [Npad][Npad]
   double beta = 0.0;           // split scale (low precision)
+  double kappa = 0.0;          // max row sum of |Ainv - (h^2/m) I| / (h^2/m) (low precision)
   int local_block = 256;
   int gemm_tile = 3;
-  int DT = 0, DH = 0;          // padded incidence widths
+  int DT = 0, DH = 0, DL = 0;  // padded incidence and Laplacian widths
 };
 
 }  // namespace
@@ -307,10 +308,21 @@ int upload_class(ClassState& c) {
   if ((rc = upload_vec(c, pt_fan, &v[7], "vt_fan"))) return rc;
   if ((rc = upload_vec(c, ph_hin, &v[9], "vh_hin"))) return rc;
   if ((rc = upload_vec(c, ph_k, &v[10], "vh_k"))) return rc;
-  if ((rc = upload_vec(c, M.lap_ptr, &v[11], "lap_ptr"))) return rc;
-  if ((rc = upload_vec(c, M.lap_col, &v[12], "lap_col"))) return rc;
-  if ((rc = upload_vec(c, cast_vec<T>(M.lap_t), &v[13], "lap_t"))) return rc;
-  if ((rc = upload_vec(c, cast_vec<T>(M.lap_b), &v[14], "lap_b"))) return rc;
+  c.DL = 0;
+  for (int i = 0; i < N; ++i) c.DL = std::max(c.DL, M.lap_ptr[i + 1] - M.lap_ptr[i]);
+  std::vector<int> pl_col((size_t)c.DL * N, N);
+  std::vector<T> pl_t((size_t)c.DL * N, T(0)), pl_b((size_t)c.DL * N, T(0));
+  for (int i = 0; i < N; ++i) {
+    for (int e = M.lap_ptr[i], k = 0; e < M.lap_ptr[i + 1]; ++e, ++k) {
+      const size_t s = (size_t)k * N + i;
+      pl_col[s] = M.lap_col[e];
+      pl_t[s] = T(M.lap_t[e]);
+      pl_b[s] = T(M.lap_b[e]);
+    }
+  }
+  if ((rc = upload_vec(c, pl_col, &v[12], "lap_col"))) return rc;
+  if ((rc = upload_vec(c, pl_t, &v[13], "lap_t"))) return rc;
+  if ((rc = upload_vec(c, pl_b, &v[14], "lap_b"))) return rc;
   return NPFEM_OK;
 }
 
@@ -333,7 +345,7 @@ ClassSlice<T> slice_of(const ClassState& c) {
   v.vt_fan = (const int*)c.view_ptrs[7];
   v.vh_hin = (const int*)c.view_ptrs[9];
   v.vh_k = (const T*)c.view_ptrs[10];
-  v.lap_ptr = (const int*)c.view_ptrs[11];
+  v.DL = c.DL;
   v.lap_col = (const int*)c.view_ptrs[12];
   v.lap_t = (const T*)c.view_ptrs[13];
   v.lap_b = (const T*)c.view_ptrs[14];
@@ -378,14 +390,32 @@ int precision_of_gemm(int prec) {
 // rho = max_c |A_c - A_0| / lambda_min(A_0), with lambda_min(A_0) >= m/h^2 + w_v
 // (both Laplacians are positive semi-definite). Low-precision operators add
 // two sweeps.
+// Correction sweeps after the global-step GEMM. Each sweep multiplies the
+// error of the solve by at most rho = rho_w + rho_lp + rho_w rho_lp, where
+// rho_w = max_c |A_c - A_0| / (m/h^2 + w_v) bounds ||A_0^-1 (A_c - A_0)|| for
+// per-cell weights (A_0 the class matrix, m/h^2 + w_v its smallest
+// eigenvalue) and rho_lp bounds the relative error of the 16-bit product:
+// 2 u kappa for the rounding of both operands (u = 2^-8 BF16, 2^-11 FP16)
+// plus, for FP16, N 2^-25 beta for operator entries in the subnormal range.
+// The GEMM plus s sweeps leave rho^(s+1) of the solution; s is the least
+// count that brings this to the unit roundoff of the state type (2^-24 FP32,
+// 2^-53 FP64). n_refine >= 0 in the options fixes the count instead.
 int choose_refine(npfem_batch_s* b, double dt, int* out) {
   if (b->n_refine_opt >= 0) {
     *out = b->n_refine_opt;
     return NPFEM_OK;
   }
-  int n = (b->gemm_kind >= 2) ? 2 : 0;
+  double rho_w = 0.0, rho_lp = 0.0;
+  if (b->gemm_kind >= 2) {
+    const double u = b->gemm_kind == 2 ? std::ldexp(1.0, -8) : std::ldexp(1.0, -11);
+    for (const ClassState& c : b->cls) {
+      if (c.n_cells == 0) continue;
+      double r = 2.0 * u * c.kappa;
+      if (b->gemm_kind == 3) r += c.N * std::ldexp(1.0, -25) * c.beta;
+      rho_lp = std::max(rho_lp, r);
+    }
+  }
   if (b->per_cell) {
-    double rho = 0.0;
     for (const ClassState& c : b->cls) {
       const double w0[4] = {c.mat.w_stretch, c.mat.w_area, c.mat.w_bend, c.mat.w_volume};
       const double lmin = c.mat.vertex_mass / (dt * dt) + c.mat.w_volume;
@@ -393,18 +423,21 @@ int choose_refine(npfem_batch_s* b, double dt, int* out) {
         const double* w = &b->weights_host[4 * (size_t)(c.cell0 + i)];
         const double dev = std::fabs(w[0] + w[1] - w0[0] - w0[1]) * c.ops.norm_t +
                            std::fabs(w[2] - w0[2]) * c.ops.norm_b + std::fabs(w[3] - w0[3]);
-        rho = std::max(rho, dev / lmin);
+        rho_w = std::max(rho_w, dev / lmin);
       }
     }
-    if (rho >= 0.9)
-      return fail(NPFEM_ERR_INVALID_ARG,
-                  "per-cell weights too far from the class material for the shared operator "
-                  "(contraction estimate %.3g); set n_refine explicitly or split the class", rho);
-    if (rho > 0.0) {
-      const double tol = b->fp64 ? 1e-15 : 1e-9;
-      const int need = (int)std::ceil(std::log(tol) / std::log(rho));
-      n = std::max(n, std::min(need, 60));
-    }
+  }
+  const double rho = rho_w + rho_lp + rho_w * rho_lp;
+  if (rho >= 0.9)
+    return fail(NPFEM_ERR_INVALID_ARG,
+                "the shared operator does not contract the correction (estimate %.3g: per-cell "
+                "weights too far from the class material, or the time step too large for the "
+                "16-bit product); set n_refine explicitly or split the class", rho);
+  int n = 0;
+  if (rho > 0.0) {
+    const double tol = b->fp64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
+    n = std::max(0, (int)std::ceil(std::log(tol) / std::log(rho)) - 1);
+    n = std::min(n, 60);
   }
   *out = n;
   return NPFEM_OK;
@@ -491,12 +524,23 @@ int factorise(npfem_batch_s* b, double dt) {
     }
     const double hm = dt * dt / c.mat.vertex_mass;
     c.beta = 0.0;
+    c.kappa = 0.0;
     if (b->gemm_kind >= 2) {
       e = launch_max_abs_split(dA, c.N, c.Npad, hm, dbeta, nullptr);
       if (e == hipSuccess) e = hipMemcpy(&c.beta, dbeta, sizeof(double), hipMemcpyDeviceToHost);
+      // kappa = max_i sum_j |Ainv_ij - hm delta_ij| / hm: the size of the part
+      // of the operator that passes through the 16-bit product
+      if (e == hipSuccess)
+        e = hipMemcpy(hA.data(), dA, sizeof(double) * hA.size(), hipMemcpyDeviceToHost);
       if (e != hipSuccess) {
         cleanup();
         return hip_fail(e, "operator scale");
+      }
+      for (int i = 0; i < c.N; ++i) {
+        double rs = 0.0;
+        for (int j = 0; j < c.N; ++j)
+          rs += std::fabs(hA[(size_t)i * c.Npad + j] - (i == j ? hm : 0.0));
+        c.kappa = std::max(c.kappa, rs / hm);
       }
     }
     if (!c.op) {

@@ -30,10 +30,13 @@ struct ClassView {
                        // padding N | N << 16 (a zero record in the kernel's LDS)
   const int* vh_hin;   // [DH][N] hinge index (0 in padding)
   const T* vh_k;       // [DH][N] stencil coefficient of the vertex (0 in padding)
-  const int* lap_ptr;  // [N+1] CSR of the Laplacian pattern (diagonal included)
-  const int* lap_col;
-  const T* lap_t;      // sum_t A_t G_t G_t^T entries
-  const T* lap_b;      // sum_e c_e K_e K_e^T entries
+  // Rows of the two Laplacians on their joint pattern (diagonal included),
+  // padded to a fixed width DL, slot-major [DL][N]; padding entries have
+  // column N and coefficient 0.
+  int DL;
+  const int* lap_col;  // [DL][N]
+  const T* lap_t;      // [DL][N] sum_t A_t G_t G_t^T entries
+  const T* lap_b;      // [DL][N] sum_e c_e K_e K_e^T entries
   double vol_rest;
 };
 
