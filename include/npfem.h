@@ -214,8 +214,10 @@ int npfem_get_volume(npfem_batch b, double* host_out);
 
 /* Launch configuration chosen for mesh class cls (after the first step, which
  * runs the autotuner when NPFEM_OPT_AUTOTUNE is set): out[0] local-step
- * workgroup size, out[1] / out[2] global-step GEMM tile rows / columns,
- * out[3] correction sweeps per global solve. Host only. */
+ * workgroup size, out[1] / out[2] global-step GEMM tile rows / columns
+ * (rows 0: the column-stationary kernel, out[2] columns per workgroup, whole
+ * operator per workgroup), out[3] correction sweeps per global solve. Host
+ * only. */
 int npfem_batch_config(npfem_batch b, int32_t cls, int32_t out[4]);
 
 /* Pins the launch configuration of class cls (same layout as

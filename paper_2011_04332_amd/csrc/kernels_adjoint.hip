@@ -128,15 +128,22 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
       if (v < N) {
         // (H z)_v = (1/6) sum over the fan of (z_b x p_c + p_b x z_c)
         T hl[3] = {T(0), T(0), T(0)}, hg[3] = {T(0), T(0), T(0)};
-        const int* __restrict__ fix = cv.vt_fan + v;
-        for (int k = 0; k < DT; ++k) {
-          const int bc = fix[k * N];
-          const int ib = bc & 0xffff, ic = bc >> 16;
-          const V4<T> pb = ps[ib], pc = ps[ic];
-          cross_acc(ls[ib], pc, hl);
-          cross_acc(pb, ls[ic], hl);
-          cross_acc(gs[ib], pc, hg);
-          cross_acc(pb, gs[ic], hg);
+        const int* __restrict__ fix = cv.vt_fan + v * DT;
+        for (int k0 = 0; k0 < DT; k0 += 8) {
+          int bcs[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) bcs[e] = fix[min(k0 + e, DT - 1)];
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            if (k0 + e >= DT) break;
+            const int ib = bcs[e] & 0xffff, ic = bcs[e] >> 16;
+            const V4<T> pb = ps[ib], pc = ps[ic];
+            cross_acc(ls[ib], pc, hl);
+            cross_acc(pb, ls[ic], hl);
+            cross_acc(gs[ib], pc, hg);
+            cross_acc(pb, gs[ic], hg);
+          }
         }
         const V4<T> l = ls[v];
         const T lv[3] = {l.x, l.y, l.z};
@@ -168,8 +175,10 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
   // ---- triangles: strain + area ----
   for (int base = 0; base < F; base += L.tch) {
     const int nt = min(L.tch, F - base);
+    int4 idn = tid < nt ? cv.tri_v[base + tid] : int4{0, 0, 0, 0};
     for (int t = base + tid; t < base + nt; t += BLOCK) {
-      const int4 id = cv.tri_v[t];
+      const int4 id = idn;
+      if (t + BLOCK < base + nt) idn = cv.tri_v[t + BLOCK];
       const V4<T> r0 = reinterpret_cast<const V4<T>*>(cv.tri_rec)[2 * t];
       const V4<T> r1 = reinterpret_cast<const V4<T>*>(cv.tri_rec)[2 * t + 1];
       const T g00 = r0.x, g01 = r0.y, g10 = r0.z, g11 = r0.w, g20 = r1.x, g21 = r1.y;
@@ -221,16 +230,27 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
       if (v < N) {
-        const int* __restrict__ tix = cv.vt_tri + v;
-        const V2<T>* __restrict__ gix = reinterpret_cast<const V2<T>*>(cv.vt_g) + v;
-        for (int k = 0; k < DT; ++k) {
-          const int t = tix[k * N] - base;
-          const V2<T> g2 = gix[k * N];
-          if (!whole && (t < 0 || t >= nt)) continue;
-          const T* w6 = work + 6 * t;
-          acc[j][0] += g2.x * w6[0] + g2.y * w6[1];
-          acc[j][1] += g2.x * w6[2] + g2.y * w6[3];
-          acc[j][2] += g2.x * w6[4] + g2.y * w6[5];
+        const int* __restrict__ tix = cv.vt_tri + v * DT;
+        const V2<T>* __restrict__ gix = reinterpret_cast<const V2<T>*>(cv.vt_g) + v * DT;
+        for (int k0 = 0; k0 < DT; k0 += 8) {
+          int ts[8];
+          V2<T> gs2[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            ts[e] = tix[min(k0 + e, DT - 1)];
+            gs2[e] = gix[min(k0 + e, DT - 1)];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            if (k0 + e >= DT) break;
+            const int t = ts[e] - base;
+            if (!whole && (t < 0 || t >= nt)) continue;
+            const T* w6 = work + 6 * t;
+            acc[j][0] += gs2[e].x * w6[0] + gs2[e].y * w6[1];
+            acc[j][1] += gs2[e].x * w6[2] + gs2[e].y * w6[3];
+            acc[j][2] += gs2[e].x * w6[4] + gs2[e].y * w6[5];
+          }
         }
       }
     }
@@ -241,8 +261,10 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
   for (int base = 0; base < E; base += L.hch) {
     const int ne = min(L.hch, E - base);
     V4<T>* ys = reinterpret_cast<V4<T>*>(work);
+    int4 idn = tid < ne ? cv.hin_v[base + tid] : int4{0, 0, 0, 0};
     for (int e = base + tid; e < base + ne; e += BLOCK) {
-      const int4 id = cv.hin_v[e];
+      const int4 id = idn;
+      if (e + BLOCK < base + ne) idn = cv.hin_v[e + BLOCK];
       const V4<T> r0 = reinterpret_cast<const V4<T>*>(cv.hin_rec)[2 * e];
       const V4<T> r1 = reinterpret_cast<const V4<T>*>(cv.hin_rec)[2 * e + 1];
       const T k0 = r0.x, k1 = r0.y, k2 = r0.z, k3 = r0.w, ce = r1.x, rr = r1.y;
@@ -282,16 +304,27 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
       if (v < N) {
-        const int* __restrict__ hix = cv.vh_hin + v;
-        const T* __restrict__ kix = cv.vh_k + v;
-        for (int k = 0; k < DH; ++k) {
-          const int hh = hix[k * N] - base;
-          const T kk = kix[k * N];
-          if (!whole && (hh < 0 || hh >= ne)) continue;
-          const V4<T> y = ys[hh];
-          acc[j][0] += kk * y.x;
-          acc[j][1] += kk * y.y;
-          acc[j][2] += kk * y.z;
+        const int* __restrict__ hix = cv.vh_hin + v * DH;
+        const T* __restrict__ kix = cv.vh_k + v * DH;
+        for (int k0 = 0; k0 < DH; k0 += 8) {
+          int hs[8];
+          T ks[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            hs[e] = hix[min(k0 + e, DH - 1)];
+            ks[e] = kix[min(k0 + e, DH - 1)];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            if (k0 + e >= DH) break;
+            const int hh = hs[e] - base;
+            if (!whole && (hh < 0 || hh >= ne)) continue;
+            const V4<T> y = ys[hh];
+            acc[j][0] += ks[e] * y.x;
+            acc[j][1] += ks[e] * y.y;
+            acc[j][2] += ks[e] * y.z;
+          }
         }
       }
     }

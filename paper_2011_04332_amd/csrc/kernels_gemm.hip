@@ -67,7 +67,7 @@ __device__ __forceinline__ void xcd_tile(int& mt, int& nt) {
 
 // ---------------------------------------------------------------- FP32/FP64
 template <typename T, int BM, int BN>
-__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
+__global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 1)) gemm_kernel(GemmArgs g) {
   constexpr int BK = 16;
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
   constexpr int VE = 16 / sizeof(T);  // elements per 16-byte vector
@@ -355,12 +355,375 @@ __global__ void __launch_bounds__(256) gemm_lp_kernel(GemmArgs g) {
   }
 }
 
+// ------------------------------------------------------- column-stationary
+// The global step is a tall-skinny product: one Npad x Npad operator against
+// thousands of columns. Here one workgroup owns RS_NG * 16 consecutive
+// columns (16 cells' three coordinates for RS_NG = 3) for the whole product
+// and keeps them in LDS; the operator, which every workgroup needs whole,
+// streams from L2 (1.7 MB in FP32, 0.9 MB in 16 bits: every XCD's L2 holds
+// it) in 16-row blocks straight into MFMA operand registers, several k-steps
+// ahead of its use. 12288 columns make 256 workgroups, one per CU, so there
+// is no tile quantisation; the four waves split the row blocks, and the row
+// blocks left over after an even split are split by column group.
+constexpr int RS_NG = 3;
+constexpr int kNumTilesTiled = 13;  // tile ids below are tiled shapes, this one column-stationary
+
+// LDS column strides: FP32 columns start 4 banks apart (stride = 4 mod 64
+// words), 16-bit columns likewise (stride = 8 mod 128 halves), so the 16
+// lanes that read one k-slice of 16 columns hit 16 disjoint bank quads.
+__host__ __device__ inline int rs_stride_f32(int npad) { return npad + ((4 - npad) % 64 + 64) % 64; }
+__host__ __device__ inline int rs_k32(int npad) { return (npad + 31) / 32 * 32; }
+__host__ __device__ inline int rs_stride_16(int npad) {
+  const int k = rs_k32(npad);
+  return k + ((8 - k) % 128 + 128) % 128;
+}
+
+size_t rs_lds_bytes(int kind, int npad) {
+  if (kind == 0) return sizeof(float) * RS_NG * 16 * (size_t)rs_stride_f32(npad);
+  if (kind >= 2) return 2 * RS_NG * 16 * (size_t)rs_stride_16(npad) + sizeof(float) * RS_NG * 16;
+  return 0;
+}
+
+// Rows [16 rb, 16 (rb + NR)) of column groups [g0, g0 + NGU) (FP32). Lane l
+// feeds the MFMA k-index l/16 with k = k0 + 4 (l/16) + j at sub-step j, for A
+// and B alike, so one 16-byte load covers four sub-steps; every B fragment
+// read from LDS serves NR row blocks. With a single row block and column
+// group the four sub-steps accumulate separately (independent MFMA chains)
+// and are summed at the end.
+template <int NR, int NGU>
+__device__ __forceinline__ void rs_rows_f32(const float* __restrict__ A, const float* Bs, int Kp,
+                                            int Npad, int rb, int g0, float* __restrict__ C, int n0,
+                                            int ncols, int mode, int lane) {
+  constexpr int NJ = (NR * NGU == 1) ? 4 : 1;
+  constexpr int D = 4;  // prefetch distance in 16-k groups
+  floatx4 acc[NR][NGU][NJ];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int u = 0; u < NGU; ++u)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) acc[r][u][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const float* arow[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    arow[r] = A + (size_t)((rb + r) * 16 + (lane & 15)) * Npad + 4 * (lane >> 4);
+  const float* bcol[NGU];
+#pragma unroll
+  for (int u = 0; u < NGU; ++u) bcol[u] = Bs + ((g0 + u) * 16 + (lane & 15)) * Kp + 4 * (lane >> 4);
+  const int nkg = Npad / 16;
+  // Straight-line prefetch: out-of-range prefetches re-read the last group
+  // (clamped address, value unused), so the loop body has no branches and the
+  // compiler can wait for exactly the load it needs.
+  auto load_a = [&](int r, int kg) {
+    return *reinterpret_cast<const float4*>(arow[r] + 16 * min(kg, nkg - 1));
+  };
+  auto step = [&](int kg, const float4 (&a)[NR]) {
+    float4 b[NGU];
+#pragma unroll
+    for (int u = 0; u < NGU; ++u) b[u] = *reinterpret_cast<const float4*>(bcol[u] + 16 * kg);
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int u = 0; u < NGU; ++u)
+        acc[r][u][0 % NJ] = Mfma4<float>::run(a[r].x, b[u].x, acc[r][u][0 % NJ]);
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int u = 0; u < NGU; ++u)
+        acc[r][u][1 % NJ] = Mfma4<float>::run(a[r].y, b[u].y, acc[r][u][1 % NJ]);
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int u = 0; u < NGU; ++u)
+        acc[r][u][2 % NJ] = Mfma4<float>::run(a[r].z, b[u].z, acc[r][u][2 % NJ]);
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int u = 0; u < NGU; ++u)
+        acc[r][u][3 % NJ] = Mfma4<float>::run(a[r].w, b[u].w, acc[r][u][3 % NJ]);
+  };
+  // two register sets: the loads for the next D groups are issued (and kept
+  // ahead of the scheduler) before the current D groups are multiplied
+  float4 cur[D][NR], nxt[D][NR];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) cur[i][r] = load_a(r, i);
+  int kg = 0;
+  for (; kg + D <= nkg; kg += D) {
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) nxt[i][r] = load_a(r, kg + D + i);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) step(kg + i, cur[i]);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) cur[i][r] = nxt[i][r];
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+    if (i < nkg - kg) step(kg + i, cur[i]);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+#pragma unroll
+    for (int u = 0; u < NGU; ++u) {
+#pragma unroll
+      for (int j = 1; j < NJ; ++j) acc[r][u][0] += acc[r][u][j];
+      const int n = n0 + (g0 + u) * 16 + (lane & 15);
+      if (n >= ncols) continue;
+      float4* c =
+          reinterpret_cast<float4*>(C + (size_t)n * Npad + (rb + r) * 16 + 4 * (lane >> 4));
+      const float4 v{acc[r][u][0][0], acc[r][u][0][1], acc[r][u][0][2], acc[r][u][0][3]};
+      if (mode == EPI_ADD) {
+        float4 o = *c;
+        o.x += v.x;
+        o.y += v.y;
+        o.z += v.z;
+        o.w += v.w;
+        *c = o;
+      } else {
+        *c = v;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) gemm_rs_f32_kernel(GemmArgs g) {
+  extern __shared__ float rs_lds[];
+  const float* __restrict__ A = static_cast<const float*>(g.A);
+  const float* __restrict__ B = static_cast<const float*>(g.B);
+  float* __restrict__ C = static_cast<float*>(g.C);
+  const int Npad = g.Npad, ncols = g.ncols, Kp = rs_stride_f32(Npad);
+  const int n0 = blockIdx.x * RS_NG * 16;
+  const int tid = threadIdx.x;
+  // staging: 8 loads per thread in flight at a time (clamped addresses,
+  // values outside the matrix replaced by zeros, no branches)
+  const int nv = Npad / 4;  // 16-byte vectors per column
+  const int total = RS_NG * 16 * nv;
+  for (int i0 = tid; i0 < total; i0 += 256 * 8) {
+    float4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = min(i0 + 256 * u, total - 1);
+      const int n = i / nv, kv = i - n * nv;
+      v[u] = *reinterpret_cast<const float4*>(B + (size_t)min(n0 + n, ncols - 1) * Npad + 4 * kv);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + 256 * u;
+      if (i < total) {
+        const int n = i / nv, kv = i - n * nv;
+        if (n0 + n >= ncols) v[u] = float4{0.f, 0.f, 0.f, 0.f};
+        *reinterpret_cast<float4*>(rs_lds + n * Kp + 4 * kv) = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  // row blocks in pairs, the pairs split evenly over the four waves; the
+  // remaining row blocks one column group at a time
+  const int wave = tid >> 6, lane = tid & 63;
+  const int nrb = Npad / 16, full = nrb & ~7;
+  for (int rb = 2 * wave; rb < full; rb += 8)
+    rs_rows_f32<2, RS_NG>(A, rs_lds, Kp, Npad, rb, 0, C, n0, ncols, g.mode, lane);
+  for (int u = wave; u < (nrb - full) * RS_NG; u += 4)
+    rs_rows_f32<1, 1>(A, rs_lds, Kp, Npad, full + u / RS_NG, u % RS_NG, C, n0, ncols, g.mode, lane);
+}
+
+// 16-bit version: the split operator Bt (16-bit, [Npad][Npad]) against the
+// columns converted once into LDS (each scaled by a power of two as in the
+// tiled kernel), k-steps of 32 (16x16x32 MFMA), k beyond Npad zero. The
+// epilogue applies C = hm (B + beta / s_n Bt B) with B re-read in FP32.
+template <typename L, int NGU>
+__device__ __forceinline__ void rs_rows_lp(const L* __restrict__ A, const L* Bs, int Kp, int Npad,
+                                           int rb, int g0, const float* __restrict__ B,
+                                           float* __restrict__ C, const float* sc, int n0,
+                                           int ncols, const GemmArgs& g, int lane) {
+  typedef typename Mfma32<L>::vec_t vec_t;
+  constexpr int NJ = NGU == 1 ? 2 : 1;
+  constexpr int D = 12;  // prefetch distance in 32-k steps
+  floatx4 acc[NGU][NJ];
+#pragma unroll
+  for (int u = 0; u < NGU; ++u)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[u][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int kl = 8 * (lane >> 4);
+  const L* __restrict__ arow = A + (size_t)(rb * 16 + (lane & 15)) * Npad + kl;
+  const L* bcol[NGU];
+#pragma unroll
+  for (int u = 0; u < NGU; ++u) bcol[u] = Bs + ((g0 + u) * 16 + (lane & 15)) * Kp + kl;
+  const int nks = rs_k32(Npad) / 32;
+  // Straight-line prefetch as in the FP32 version; k >= Npad (the last step
+  // when Npad is an odd multiple of 16) reads a clamped, valid address and
+  // is replaced by zeros.
+  auto load_a = [&](int ks) {
+    const int k = 32 * min(ks, nks - 1) + kl;
+    vec_t a = *reinterpret_cast<const vec_t*>(arow - kl + min(k, Npad - 8));
+    if (k >= Npad) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) a[e] = L(0.0f);
+    }
+    return a;
+  };
+  auto step = [&](int ks, const vec_t& a) {
+#pragma unroll
+    for (int u = 0; u < NGU; ++u) {
+      const vec_t b = *reinterpret_cast<const vec_t*>(bcol[u] + 32 * ks);
+      acc[u][ks % NJ] = Mfma32<L>::run(a, b, acc[u][ks % NJ]);
+    }
+  };
+  vec_t cur[D], nxt[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) cur[i] = load_a(i);
+  int ks = 0;
+  for (; ks + D <= nks; ks += D) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) nxt[i] = load_a(ks + D + i);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) step(ks + i, cur[i]);
+#pragma unroll
+    for (int i = 0; i < D; ++i) cur[i] = nxt[i];
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+    if (i < nks - ks) step(ks + i, cur[i]);
+  const float hm = (float)g.hm, beta = (float)g.beta;
+#pragma unroll
+  for (int u = 0; u < NGU; ++u) {
+#pragma unroll
+    for (int j = 1; j < NJ; ++j) acc[u][0] += acc[u][j];
+    const int nl = (g0 + u) * 16 + (lane & 15);
+    const int n = n0 + nl;
+    if (n >= ncols) continue;
+    const int m = rb * 16 + 4 * (lane >> 4);
+    const float unscale = beta / sc[nl];
+    const float4 bv = *reinterpret_cast<const float4*>(B + (size_t)n * Npad + m);
+    float4* c = reinterpret_cast<float4*>(C + (size_t)n * Npad + m);
+    float4 v;
+    v.x = hm * (bv.x + unscale * acc[u][0][0]);
+    v.y = hm * (bv.y + unscale * acc[u][0][1]);
+    v.z = hm * (bv.z + unscale * acc[u][0][2]);
+    v.w = hm * (bv.w + unscale * acc[u][0][3]);
+    if (g.mode == EPI_SPLIT_ADD) {
+      float4 o = *c;
+      o.x += v.x;
+      o.y += v.y;
+      o.z += v.z;
+      o.w += v.w;
+      *c = o;
+    } else {
+      *c = v;
+    }
+  }
+}
+
+template <typename L>
+__global__ void __launch_bounds__(256) gemm_rs_lp_kernel(GemmArgs g) {
+  extern __shared__ float rs_lds_lp[];
+  const L* __restrict__ A = static_cast<const L*>(g.A);
+  const float* __restrict__ B = static_cast<const float*>(g.B);
+  float* __restrict__ C = static_cast<float*>(g.C);
+  const int Npad = g.Npad, ncols = g.ncols, Kp = rs_stride_16(Npad), K32 = rs_k32(Npad);
+  const int n0 = blockIdx.x * RS_NG * 16;
+  const int tid = threadIdx.x;
+  float* sc = rs_lds_lp;                                      // [RS_NG * 16] column scales
+  L* Bs = reinterpret_cast<L*>(rs_lds_lp + RS_NG * 16);       // [RS_NG * 16][Kp]
+  for (int j = tid; j < RS_NG * 16; j += 256) {
+    float s = 1.0f;
+    const int n = n0 + j;
+    if (g.colscale && n < ncols) {
+      const float mx = g.colscale[n];
+      if (mx > 0.0f && isfinite(mx)) s = exp2f(-ceilf(log2f(mx)));
+    }
+    sc[j] = s;
+  }
+  __syncthreads();
+  // staging: 8 vector pairs per thread in flight at a time (clamped
+  // addresses, values outside the matrix replaced by zeros, no branches)
+  const int nv = K32 / 8;  // 8-element vectors per column
+  const int total = RS_NG * 16 * nv;
+  for (int i0 = tid; i0 < total; i0 += 256 * 8) {
+    float4 lo[8], hi[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = min(i0 + 256 * u, total - 1);
+      const int n = i / nv, kv = i - n * nv;
+      const float* src = B + (size_t)min(n0 + n, ncols - 1) * Npad + min(8 * kv, Npad - 8);
+      lo[u] = *reinterpret_cast<const float4*>(src);
+      hi[u] = *reinterpret_cast<const float4*>(src + 4);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + 256 * u;
+      if (i < total) {
+        const int n = i / nv, kv = i - n * nv;
+        const int k = 8 * kv;
+        const bool in = n0 + n < ncols && k < Npad;
+        const float s = in ? sc[n] : 0.0f;
+        typename Mfma32<L>::vec_t v;
+        v[0] = L(lo[u].x * s);
+        v[1] = L(lo[u].y * s);
+        v[2] = L(lo[u].z * s);
+        v[3] = L(lo[u].w * s);
+        v[4] = L(hi[u].x * s);
+        v[5] = L(hi[u].y * s);
+        v[6] = L(hi[u].z * s);
+        v[7] = L(hi[u].w * s);
+        *reinterpret_cast<typename Mfma32<L>::vec_t*>(Bs + n * Kp + k) = v;
+      }
+    }
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63;
+  const int nrb = Npad / 16, full = nrb & ~3;
+  for (int rb = wave; rb < full; rb += 4)
+    rs_rows_lp<L, RS_NG>(A, Bs, Kp, Npad, rb, 0, B, C, sc, n0, ncols, g, lane);
+  for (int u = wave; u < (nrb - full) * RS_NG; u += 4)
+    rs_rows_lp<L, 1>(A, Bs, Kp, Npad, full + u / RS_NG, u % RS_NG, B, C, sc, n0, ncols, g, lane);
+}
+
+static const void* rs_kernel(int kind) {
+  return kind == 0 ? (const void*)gemm_rs_f32_kernel
+       : kind == 2 ? (const void*)gemm_rs_lp_kernel<__bf16>
+       : kind == 3 ? (const void*)gemm_rs_lp_kernel<_Float16>
+                   : nullptr;
+}
+
+// Raises the dynamic-LDS limit of the column-stationary kernel to what a
+// class of Npad rows needs (not a stream operation: call before capture).
+hipError_t gemm_prepare(int kind, int tile, int npad) {
+  if (tile != kNumTilesTiled) return hipSuccess;
+  const size_t smem = rs_lds_bytes(kind, npad);
+  if (!rs_kernel(kind) || smem == 0 || smem > 160 * 1024) return hipErrorInvalidValue;
+  if (smem <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(rs_kernel(kind), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)smem);
+}
+
+static hipError_t run_gemm_rs(int kind, const GemmArgs& g, hipStream_t st) {
+  const size_t smem = rs_lds_bytes(kind, g.Npad);
+  const void* fn = rs_kernel(kind);
+  if (!fn || smem == 0 || smem > 160 * 1024) return hipErrorInvalidValue;
+  GemmArgs a = g;
+  void* args[] = {&a};
+  const int blocks = (g.ncols + RS_NG * 16 - 1) / (RS_NG * 16);
+  return hipLaunchKernel(fn, dim3(blocks), dim3(256), args, smem, st);
+}
+
 // ---------------------------------------------------------------- dispatch
 struct TileShape {
   int bm, bn;
 };
-static const TileShape kTiles[] = {{64, 64},  {64, 128}, {128, 64}, {128, 128},
-                                   {96, 64},  {96, 128}, {224, 32}, {224, 64}};
+// Tiled shapes, then (last entry, bm = 0) the column-stationary kernel with
+// RS_NG * 16 columns per workgroup (FP32 and 16-bit only).
+static const TileShape kTiles[] = {{64, 64},  {64, 128}, {128, 64}, {128, 128}, {96, 64},
+                                   {96, 128}, {224, 32}, {224, 64}, {96, 96},   {224, 96},
+                                   {224, 128}, {64, 96}, {128, 96}, {0, RS_NG * 16}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 int gemm_num_tiles(int) { return kNumTiles; }
@@ -407,6 +770,12 @@ hipError_t launch_gemm(int kind, int tile, const GemmArgs& g, hipStream_t st) {
     case 5: return run_kind<96, 128>(kind, g, st);
     case 6: return run_kind<224, 32>(kind, g, st);
     case 7: return run_kind<224, 64>(kind, g, st);
+    case 8: return run_kind<96, 96>(kind, g, st);
+    case 9: return run_kind<224, 96>(kind, g, st);
+    case 10: return run_kind<224, 128>(kind, g, st);
+    case 11: return run_kind<64, 96>(kind, g, st);
+    case 12: return run_kind<128, 96>(kind, g, st);
+    case kNumTilesTiled: return run_gemm_rs(kind, g, st);
     default: return hipErrorInvalidValue;
   }
 }

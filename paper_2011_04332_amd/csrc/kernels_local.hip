@@ -32,14 +32,31 @@ struct LocalLaunch {
   int hch;  // hinges per LDS chunk
 };
 
+// KT, KH > 0: compile-time incidence widths (triangles and hinges per
+// vertex; they must equal cv.DT and cv.DH), so that every incidence entry of
+// a vertex is fetched in one memory round trip before the gathers use them.
+// 0: widths read at run time.
+// Occupancy target (waves per SIMD) for FP32, which sets the register
+// budget: with 256 threads the LDS of a 642-vertex cell allows three
+// workgroups per CU (three waves per SIMD); with 128 or 512 threads four
+// waves per SIMD (at most 128 registers) keep the incidence prefetches of
+// two vertices in registers. Six or more vertices per thread means a large
+// mesh whose LDS allows one workgroup per CU: no register cap.
 template <typename T, int BLOCK, int VPT>
-__global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
+constexpr int local_waves_per_eu() {
+  return VPT >= 6 ? 1 : sizeof(T) == 4 ? (BLOCK == 256 ? 3 : 4) : 2;
+}
+
+template <typename T, int BLOCK, int VPT, int KT, int KH>
+__global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
+    local_kernel(LocalLaunch<T> L) {
   extern __shared__ double smem_local[];
   constexpr int NW = BLOCK / kWave;
   constexpr int NEWTON = sizeof(T) == 8 ? 4 : 3;  // area multiplier (projections.h)
   const LocalArgs<T>& a = L.a;
   const ClassView<T>& cv = a.cs.cv;
-  const int N = cv.N, Npad = cv.Npad, F = cv.F, E = cv.E, DT = cv.DT, DH = cv.DH;
+  const int N = cv.N, Npad = cv.Npad, F = cv.F, E = cv.E;
+  const int DT = KT > 0 ? KT : cv.DT, DH = KH > 0 ? KH : cv.DH;
   const int tid = threadIdx.x;
   const int lc = blockIdx.x;
   const int cell = a.cs.cell0 + lc;
@@ -100,8 +117,8 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
   {
     V4<T>* ps = reinterpret_cast<V4<T>*>(work);
     T g[VPT][3], p[VPT][3];
-    volume_project<T, BLOCK, VPT, false>(cv, qs, ps, red, g, p, a.max_vol_iter, a.vol_tol,
-                                         a.vol_abs, bad);
+    volume_project<T, BLOCK, VPT, false, KT>(cv, qs, ps, red, g, p, a.max_vol_iter, a.vol_tol,
+                                             a.vol_abs, bad);
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
@@ -123,10 +140,14 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
   // ---- triangles: strain + area ----
   for (int base = 0; base < F; base += L.tch) {
     const int nt = min(L.tch, F - base);
+    // the next element's vertex ids are fetched one iteration ahead, so that
+    // their round trip overlaps the current element's work
+    int4 idn = tid < nt ? cv.tri_v[base + tid] : int4{0, 0, 0, 0};
     for (int t = base + tid; t < base + nt; t += BLOCK) {
-      const int4 id = cv.tri_v[t];
+      const int4 id = idn;
       const V4<T> r0 = reinterpret_cast<const V4<T>*>(cv.tri_rec)[2 * t];
       const V4<T> r1 = reinterpret_cast<const V4<T>*>(cv.tri_rec)[2 * t + 1];
+      if (t + BLOCK < base + nt) idn = cv.tri_v[t + BLOCK];
       const T g00 = r0.x, g01 = r0.y, g10 = r0.z, g11 = r0.w, g20 = r1.x, g21 = r1.y;
       const T area = r1.z;
       const V4<T> qa = qs[id.x], qb = qs[id.y], qc = qs[id.z];
@@ -170,31 +191,54 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
     }
     __syncthreads();
     const bool whole = (nt == F);  // one chunk: every entry is in range
+    auto tri_add = [&](int j, int t, V2<T> g2) {
+      const T* w = work + 6 * t;
+      acc[j][0] += g2.x * w[0] + g2.y * w[1];
+      acc[j][1] += g2.x * w[2] + g2.y * w[3];
+      acc[j][2] += g2.x * w[4] + g2.y * w[5];
+    };
+    if constexpr (KT > 0) {
+      if (whole) {
+        // the entries of vertex j + 1 are fetched before vertex j is summed
+        // (two register sets), so one round trip overlaps the previous work
+        int tt[2][KT];
+        V2<T> gg[2][KT];
+        auto fetch = [&](int j, int set) {
+          const int v = min(tid + j * BLOCK, N - 1);  // clamped: always a valid row
 #pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-      const int v = tid + j * BLOCK;
-      if (v < N) {
-        const int* __restrict__ tix = cv.vt_tri + v;
-        const V2<T>* __restrict__ gix = reinterpret_cast<const V2<T>*>(cv.vt_g) + v;
-        if (whole) {
-#pragma unroll 6
-          for (int k = 0; k < DT; ++k) {
-            const int t = tix[k * N];
-            const V2<T> g2 = gix[k * N];
-            const T* w = work + 6 * t;
-            acc[j][0] += g2.x * w[0] + g2.y * w[1];
-            acc[j][1] += g2.x * w[2] + g2.y * w[3];
-            acc[j][2] += g2.x * w[4] + g2.y * w[5];
+          for (int u = 0; u < KT; ++u) {
+            tt[set][u] = cv.vt_tri[v * KT + u];
+            gg[set][u] = reinterpret_cast<const V2<T>*>(cv.vt_g)[v * KT + u];
           }
-        } else {
-          for (int k = 0; k < DT; ++k) {
-            const int t = tix[k * N] - base;
-            const V2<T> g2 = gix[k * N];
-            if (t < 0 || t >= nt) continue;
-            const T* w = work + 6 * t;
-            acc[j][0] += g2.x * w[0] + g2.y * w[1];
-            acc[j][1] += g2.x * w[2] + g2.y * w[3];
-            acc[j][2] += g2.x * w[4] + g2.y * w[5];
+        };
+        fetch(0, 0);
+#pragma unroll
+        for (int j = 0; j < VPT; ++j) {
+          if (j + 1 < VPT) fetch(j + 1, (j + 1) & 1);
+          __builtin_amdgcn_sched_barrier(0);
+          if (tid + j * BLOCK < N) {
+#pragma unroll
+            for (int u = 0; u < KT; ++u) tri_add(j, tt[j & 1][u], gg[j & 1][u]);
+          }
+        }
+      }
+    }
+    if (KT == 0 || !whole) {
+#pragma unroll
+      for (int j = 0; j < VPT; ++j) {
+        const int v = tid + j * BLOCK;
+        if (v < N) {
+          const int* __restrict__ tix = cv.vt_tri + v * DT;
+          const V2<T>* __restrict__ gix = reinterpret_cast<const V2<T>*>(cv.vt_g) + v * DT;
+          if (whole) {
+#pragma unroll 6
+            for (int k = 0; k < DT; ++k) tri_add(j, tix[k], gix[k]);
+          } else {
+            for (int k = 0; k < DT; ++k) {
+              const int t = tix[k] - base;
+              if (t < 0 || t >= nt) continue;
+              tri_add(j, t, gix[k]);
+            }
           }
         }
       }
@@ -216,10 +260,12 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
   for (int base = 0; base < E; base += L.hch) {
     const int ne = min(L.hch, E - base);
     V4<T>* ys = reinterpret_cast<V4<T>*>(work);
+    int4 idn = tid < ne ? cv.hin_v[base + tid] : int4{0, 0, 0, 0};
     for (int e = base + tid; e < base + ne; e += BLOCK) {
-      const int4 id = cv.hin_v[e];
+      const int4 id = idn;
       const V4<T> r0 = reinterpret_cast<const V4<T>*>(cv.hin_rec)[2 * e];
       const V4<T> r1 = reinterpret_cast<const V4<T>*>(cv.hin_rec)[2 * e + 1];
+      if (e + BLOCK < base + ne) idn = cv.hin_v[e + BLOCK];
       const T k0 = r0.x, k1 = r0.y, k2 = r0.z, k3 = r0.w, ce = r1.x, rr = r1.y;
       const V4<T> qi = qs[id.x], qj = qs[id.y], qk = qs[id.z], ql = qs[id.w];
       const V4<T> xi = xs[id.x], xj = xs[id.y], xk = xs[id.z], xl = xs[id.w];
@@ -250,30 +296,52 @@ __global__ void __launch_bounds__(BLOCK) local_kernel(LocalLaunch<T> L) {
     }
     __syncthreads();
     const bool whole = (ne == E);
+    auto hin_add = [&](int j, int hh, T kk) {
+      const V4<T> y = ys[hh];
+      acc[j][0] += kk * y.x;
+      acc[j][1] += kk * y.y;
+      acc[j][2] += kk * y.z;
+    };
+    if constexpr (KH > 0) {
+      if (whole) {
+        int hh[2][KH];
+        T kk[2][KH];
+        auto fetch = [&](int j, int set) {
+          const int v = min(tid + j * BLOCK, N - 1);
 #pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-      const int v = tid + j * BLOCK;
-      if (v < N) {
-        const int* __restrict__ hix = cv.vh_hin + v;
-        const T* __restrict__ kix = cv.vh_k + v;
-        if (whole) {
-#pragma unroll 4
-          for (int k = 0; k < DH; ++k) {
-            const V4<T> y = ys[hix[k * N]];
-            const T kk = kix[k * N];
-            acc[j][0] += kk * y.x;
-            acc[j][1] += kk * y.y;
-            acc[j][2] += kk * y.z;
+          for (int u = 0; u < KH; ++u) {
+            hh[set][u] = cv.vh_hin[v * KH + u];
+            kk[set][u] = cv.vh_k[v * KH + u];
           }
-        } else {
-          for (int k = 0; k < DH; ++k) {
-            const int hh = hix[k * N] - base;
-            const T kk = kix[k * N];
-            if (hh < 0 || hh >= ne) continue;
-            const V4<T> y = ys[hh];
-            acc[j][0] += kk * y.x;
-            acc[j][1] += kk * y.y;
-            acc[j][2] += kk * y.z;
+        };
+        fetch(0, 0);
+#pragma unroll
+        for (int j = 0; j < VPT; ++j) {
+          if (j + 1 < VPT) fetch(j + 1, (j + 1) & 1);
+          __builtin_amdgcn_sched_barrier(0);
+          if (tid + j * BLOCK < N) {
+#pragma unroll
+            for (int u = 0; u < KH; ++u) hin_add(j, hh[j & 1][u], kk[j & 1][u]);
+          }
+        }
+      }
+    }
+    if (KH == 0 || !whole) {
+#pragma unroll
+      for (int j = 0; j < VPT; ++j) {
+        const int v = tid + j * BLOCK;
+        if (v < N) {
+          const int* __restrict__ hix = cv.vh_hin + v * DH;
+          const T* __restrict__ kix = cv.vh_k + v * DH;
+          if (whole) {
+#pragma unroll 4
+            for (int k = 0; k < DH; ++k) hin_add(j, hix[k], kix[k]);
+          } else {
+            for (int k = 0; k < DH; ++k) {
+              const int hh = hix[k] - base;
+              if (hh < 0 || hh >= ne) continue;
+              hin_add(j, hh, kix[k]);
+            }
           }
         }
       }
@@ -354,25 +422,35 @@ size_t local_smem_bytes(const ClassView<T>& cv, int block) {
 template <typename T>
 using LocalFn = void (*)(LocalLaunch<T>);
 
+// Incidence widths with a compile-time instance: 6 triangles and 12 hinges
+// per vertex (every vertex of valence <= 6, e.g. subdivided icosahedra).
+constexpr int kFixedDT = 6, kFixedDH = 12;
+
+template <typename T, int BLOCK, int VPT>
+static LocalFn<T> pick_widths(int DT, int DH) {
+  if (DT == kFixedDT && DH == kFixedDH) return local_kernel<T, BLOCK, VPT, kFixedDT, kFixedDH>;
+  return local_kernel<T, BLOCK, VPT, 0, 0>;
+}
+
 template <typename T, int BLOCK>
-static LocalFn<T> pick_vpt(int N) {
+static LocalFn<T> pick_vpt(int N, int DT, int DH) {
   const int vpt = (N + BLOCK - 1) / BLOCK;
-  if (vpt <= 1) return local_kernel<T, BLOCK, 1>;
-  if (vpt <= 2) return local_kernel<T, BLOCK, 2>;
-  if (vpt <= 3) return local_kernel<T, BLOCK, 3>;
-  if (vpt <= 4) return local_kernel<T, BLOCK, 4>;
-  if (vpt <= 6) return local_kernel<T, BLOCK, 6>;
-  if (vpt <= 8) return local_kernel<T, BLOCK, 8>;
-  if (vpt <= 11) return local_kernel<T, BLOCK, 11>;
+  if (vpt <= 1) return pick_widths<T, BLOCK, 1>(DT, DH);
+  if (vpt <= 2) return pick_widths<T, BLOCK, 2>(DT, DH);
+  if (vpt <= 3) return pick_widths<T, BLOCK, 3>(DT, DH);
+  if (vpt <= 4) return pick_widths<T, BLOCK, 4>(DT, DH);
+  if (vpt <= 6) return pick_widths<T, BLOCK, 6>(DT, DH);
+  if (vpt <= 8) return local_kernel<T, BLOCK, 8, 0, 0>;
+  if (vpt <= 11) return local_kernel<T, BLOCK, 11, 0, 0>;
   return nullptr;
 }
 
 template <typename T>
-static LocalFn<T> pick_local(int N, int block) {
+static LocalFn<T> pick_local(const ClassView<T>& cv, int block) {
   switch (block) {
-    case 128: return pick_vpt<T, 128>(N);
-    case 256: return pick_vpt<T, 256>(N);
-    case 512: return pick_vpt<T, 512>(N);
+    case 128: return pick_vpt<T, 128>(cv.N, cv.DT, cv.DH);
+    case 256: return pick_vpt<T, 256>(cv.N, cv.DT, cv.DH);
+    case 512: return pick_vpt<T, 512>(cv.N, cv.DT, cv.DH);
     default: return nullptr;
   }
 }
@@ -381,7 +459,7 @@ static LocalFn<T> pick_local(int N, int block) {
 // a stream operation: call before graph capture).
 template <typename T>
 hipError_t local_prepare(const ClassView<T>& cv, int block) {
-  LocalFn<T> fn = pick_local<T>(cv.N, block);
+  LocalFn<T> fn = pick_local<T>(cv, block);
   if (!fn) return hipErrorInvalidValue;
   const size_t smem = local_smem_bytes_chunks(cv, block, nullptr, nullptr);
   if (smem > 160 * 1024) return hipErrorInvalidValue;
@@ -394,7 +472,7 @@ hipError_t local_prepare(const ClassView<T>& cv, int block) {
 template <typename T>
 hipError_t launch_local(const LocalArgs<T>& a, int block, hipStream_t st) {
   if (a.cs.n_cells == 0) return hipSuccess;
-  LocalFn<T> fn = pick_local<T>(a.cs.cv.N, block);
+  LocalFn<T> fn = pick_local<T>(a.cs.cv, block);
   if (!fn) return hipErrorInvalidValue;
   LocalLaunch<T> L;
   L.a = a;

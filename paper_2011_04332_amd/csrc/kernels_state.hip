@@ -109,14 +109,27 @@ __global__ void __launch_bounds__(256) residual_kernel(ClassSlice<T> cs, const T
       a0 = diag * (double)sx[v];
       a1 = diag * (double)sy[v];
       a2 = diag * (double)sz[v];
-#pragma unroll 4
-      for (int k = 0; k < DL; ++k) {
-        const int e = k * N + v;
-        const int j = lcol[e];
-        const double c = wt * (double)lt[e] + wb * (double)lb[e];
-        a0 += c * (double)sx[j];
-        a1 += c * (double)sy[j];
-        a2 += c * (double)sz[j];
+      // row entries fetched 8 at a time, one memory round trip per batch
+      // (the index past the last slot is clamped and its weight zeroed)
+      for (int k0 = 0; k0 < DL; k0 += 8) {
+        int jj[8];
+        T ct[8], cb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = min(k0 + u, DL - 1) * N + v;
+          jj[u] = lcol[e];
+          ct[u] = lt[e];
+          cb[u] = lb[e];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const double c = k0 + u < DL ? wt * (double)ct[u] + wb * (double)cb[u] : 0.0;
+          const int j = jj[u];
+          a0 += c * (double)sx[j];
+          a1 += c * (double)sy[j];
+          a2 += c * (double)sz[j];
+        }
       }
       a0 = (double)r0 - a0;
       a1 = (double)r1 - a1;

@@ -23,18 +23,56 @@ __device__ __forceinline__ T comp(const V4<T>& v, int d) {
 }
 
 // grad_v V(p) = (1/6) sum over the fan of v of p_b x p_c, (v, b, c)
-// counter-clockwise; padding fan entries point at the zero record ps[N].
-template <typename T>
+// counter-clockwise; padding fan entries point at record N (b = c gives an
+// exact zero cross product whatever the record holds). KT > 0 fixes the fan
+// width at compile time (it must equal cv.DT): all indices are fetched in
+// one round trip before any is used. KT = 0 reads cv.DT, 8 entries a time.
+template <typename T, int KT>
 __device__ __forceinline__ void volume_gradient(const ClassView<T>& cv, const V4<T>* ps, int v,
                                                 T& gx, T& gy, T& gz) {
   const int N = cv.N;
   gx = gy = gz = T(0);
-  const int* __restrict__ fix = cv.vt_fan + v;
-#pragma unroll 6
-  for (int k = 0; k < cv.DT; ++k) {
-    const int bc = fix[k * N];
+  const int* __restrict__ fix = cv.vt_fan + v * (KT > 0 ? KT : cv.DT);
+  auto add = [&](int bc) {
     const V4<T> pb = ps[bc & 0xffff];
     const V4<T> pc = ps[bc >> 16];
+    gx += pb.y * pc.z - pb.z * pc.y;
+    gy += pb.z * pc.x - pb.x * pc.z;
+    gz += pb.x * pc.y - pb.y * pc.x;
+  };
+  if constexpr (KT > 0) {
+    int bc[KT];
+#pragma unroll
+    for (int u = 0; u < KT; ++u) bc[u] = fix[u];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < KT; ++u) add(bc[u]);
+  } else {
+    const int DT = cv.DT;
+    for (int k0 = 0; k0 < DT; k0 += 8) {
+      int bc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) bc[u] = k0 + u < DT ? fix[k0 + u] : (N | (N << 16));
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k0 + u < DT) add(bc[u]);
+    }
+  }
+  gx *= T(1.0 / 6.0);
+  gy *= T(1.0 / 6.0);
+  gz *= T(1.0 / 6.0);
+}
+
+// The same sum from fan indices already in registers.
+template <typename T, int KT>
+__device__ __forceinline__ void volume_gradient_fan(const V4<T>* ps, const int (&bc)[KT], T& gx,
+                                                    T& gy, T& gz) {
+  gx = gy = gz = T(0);
+#pragma unroll
+  for (int u = 0; u < KT; ++u) {
+    const V4<T> pb = ps[bc[u] & 0xffff];
+    const V4<T> pc = ps[bc[u] >> 16];
     gx += pb.y * pc.z - pb.z * pc.y;
     gy += pb.z * pc.x - pb.x * pc.z;
     gz += pb.x * pc.y - pb.y * pc.x;
@@ -63,8 +101,9 @@ __device__ __forceinline__ void volume_gradient(const ClassView<T>& cv, const V4
 // produced p (p = q + lam g), and the value is lam. With STORE_P, ps[0..N)
 // also holds p and ps[N] = 0, behind a barrier. Without it, ps is scratch
 // (written only when a second iteration runs) and no thread reads it any
-// more. red: 8 * (BLOCK / 64) doubles. Call from uniform control flow.
-template <typename T, int BLOCK, int VPT, bool STORE_P>
+// more. red: 8 * (BLOCK / 64) doubles. KT: fan width (0 = runtime). Call
+// from uniform control flow.
+template <typename T, int BLOCK, int VPT, bool STORE_P, int KT = 0>
 __device__ double volume_project(const ClassView<T>& cv, const V4<T>* qs, V4<T>* ps, double* red,
                                  T (&g)[VPT][3], T (&pv)[VPT][3], int max_it, double vol_tol,
                                  double vol_abs, int& bad) {
@@ -75,13 +114,29 @@ __device__ double volume_project(const ClassView<T>& cv, const V4<T>* qs, V4<T>*
   for (int it = 0; it < max_it; ++it) {
     double s[3] = {0.0, 0.0, 0.0};
     double mq = 0.0;
+    // KT > 0: the fan indices of all of this thread's vertices are fetched
+    // in one round trip up front
+    int fan[VPT][KT > 0 ? KT : 1];
+    if constexpr (KT > 0) {
+#pragma unroll
+      for (int j = 0; j < VPT; ++j) {
+        const int v = min(tid + j * BLOCK, N - 1);
+#pragma unroll
+        for (int u = 0; u < KT; ++u) fan[j][u] = cv.vt_fan[v * KT + u];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
       g[j][0] = g[j][1] = g[j][2] = T(0);
       if (v < N) {
         T gx, gy, gz;
-        volume_gradient(cv, src, v, gx, gy, gz);
+        if constexpr (KT > 0) {
+          volume_gradient_fan<T, KT>(src, fan[j], gx, gy, gz);
+        } else {
+          volume_gradient<T, 0>(cv, src, v, gx, gy, gz);
+        }
         g[j][0] = gx;
         g[j][1] = gy;
         g[j][2] = gz;

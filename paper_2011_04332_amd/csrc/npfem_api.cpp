@@ -274,7 +274,7 @@ int upload_class(ClassState& c) {
   if ((rc = upload_vec(c, tri_rec, &v[1], "tri_rec"))) return rc;
   if ((rc = upload_vec(c, hin_v, &v[2], "hin_v"))) return rc;
   if ((rc = upload_vec(c, hin_rec, &v[3], "hin_rec"))) return rc;
-  // fixed-width, slot-major incidence ([slot][N]); entries keep ascending
+  // fixed-width, vertex-major incidence ([N][slot]); entries keep ascending
   // element order, padding contributes zero
   const int N = M.N;
   c.DT = 0;
@@ -287,7 +287,7 @@ int upload_class(ClassState& c) {
   std::vector<T> pt_g(2 * (size_t)c.DT * N, T(0));
   for (int i = 0; i < N; ++i) {
     for (int e = M.vt_ptr[i], k = 0; e < M.vt_ptr[i + 1]; ++e, ++k) {
-      const size_t s = (size_t)k * N + i;
+      const size_t s = (size_t)i * c.DT + k;
       pt_tri[s] = M.vt_tri[e];
       pt_fan[s] = M.vt_fan[e];
       pt_g[2 * s] = T(M.vt_g[2 * (size_t)e]);
@@ -298,7 +298,7 @@ int upload_class(ClassState& c) {
   std::vector<T> ph_k((size_t)c.DH * N, T(0));
   for (int i = 0; i < N; ++i) {
     for (int e = M.vh_ptr[i], k = 0; e < M.vh_ptr[i + 1]; ++e, ++k) {
-      const size_t s = (size_t)k * N + i;
+      const size_t s = (size_t)i * c.DH + k;
       ph_hin[s] = M.vh_hin[e];
       ph_k[s] = T(M.vh_k[e]);
     }
@@ -699,6 +699,8 @@ int prepare_kernels(npfem_batch_s* b) {
     hipError_t e = b->fp64 ? local_prepare<double>(slice_of<double>(c).cv, c.local_block)
                            : local_prepare<float>(slice_of<float>(c).cv, c.local_block);
     if (e != hipSuccess) return hip_fail(e, "local step attributes");
+    e = gemm_prepare(b->gemm_kind, c.gemm_tile, c.Npad);
+    if (e != hipSuccess) return hip_fail(e, "global step attributes");
   }
   return NPFEM_OK;
 }
@@ -746,15 +748,23 @@ int autotune(npfem_batch_s* b, double h) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0), "autotune events");
   HIP_TRY(hipEventCreate(&e1), "autotune events");
+  // best of three rounds of three launches, after one warm-up launch (that
+  // also checks that the candidate launches at all)
   auto timed = [&](auto&& launch, float* ms) -> hipError_t {
-    hipError_t e = launch();  // warm-up (and validity check)
+    hipError_t e = launch();
     if (e != hipSuccess) return e;
-    if ((e = hipEventRecord(e0, st)) != hipSuccess) return e;
-    for (int i = 0; i < 3; ++i)
-      if ((e = launch()) != hipSuccess) return e;
-    if ((e = hipEventRecord(e1, st)) != hipSuccess) return e;
-    if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
-    return hipEventElapsedTime(ms, e0, e1);
+    *ms = 1e30f;
+    for (int r = 0; r < 3; ++r) {
+      if ((e = hipEventRecord(e0, st)) != hipSuccess) return e;
+      for (int i = 0; i < 3; ++i)
+        if ((e = launch()) != hipSuccess) return e;
+      if ((e = hipEventRecord(e1, st)) != hipSuccess) return e;
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+      float t = 0.f;
+      if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) return e;
+      *ms = std::min(*ms, t);
+    }
+    return hipSuccess;
   };
   int rc = NPFEM_OK;
   for (auto& c : b->cls) {
@@ -772,6 +782,7 @@ int autotune(npfem_batch_s* b, double h) {
     float best = 1e30f;
     for (int tile = 0; tile < gemm_num_tiles(b->gemm_kind); ++tile) {
       float ms = 0.f;
+      if (gemm_prepare(b->gemm_kind, tile, c.Npad) != hipSuccess) continue;
       if (timed([&]() { return launch_gemm(b->gemm_kind, tile, g, st); }, &ms) == hipSuccess &&
           ms < best) {
         best = ms;
@@ -859,6 +870,7 @@ int adjoint_impl(npfem_batch_s* b, const void* dL_dx, const void* dL_dv, void* d
   for (auto& c : b->cls) {
     hipError_t e = local_prepare<T>(slice_of<T>(c).cv, c.local_block);
     if (e == hipSuccess) e = adjoint_prepare<T>(slice_of<T>(c).cv);
+    if (e == hipSuccess) e = gemm_prepare(b->gemm_kind, c.gemm_tile, c.Npad);
     if (e != hipSuccess) return hip_fail(e, "adjoint kernel attributes");
   }
   HIP_TRY(hipMemcpyAsync(xbar, dL_dx, sizeof(T) * sv, hipMemcpyDeviceToDevice, st), "adjoint");

@@ -19,17 +19,18 @@ struct ClassView {
   const T* tri_rec;    // [F][8]: G (3x2 row-major), area, 0
   const int4* hin_v;   // [E] (i, j, k, l)
   const T* hin_rec;    // [E][8]: K[4], c, r_rest, 0, 0
-  // Vertex incidence padded to a fixed width (slot-major [slot][N], so that
-  // threads of consecutive vertices read consecutive words); entries of a
-  // vertex are in ascending element order, padding entries contribute zero.
+  // Vertex incidence padded to a fixed width, vertex-major ([N][slot]: a
+  // thread reads its vertex's entries as one contiguous run, and a wave's
+  // runs are contiguous too); entries of a vertex are in ascending element
+  // order, padding entries contribute zero.
   int DT;              // max triangles per vertex
   int DH;              // max hinges per vertex
-  const int* vt_tri;   // [DT][N] triangle index (0 in padding)
-  const T* vt_g;       // [DT][N][2] G row of the vertex in that triangle (0 in padding)
-  const int* vt_fan;   // [DT][N] other two vertices b | c << 16, (v, b, c) counter-clockwise;
+  const int* vt_tri;   // [N][DT] triangle index (0 in padding)
+  const T* vt_g;       // [N][DT][2] G row of the vertex in that triangle (0 in padding)
+  const int* vt_fan;   // [N][DT] other two vertices b | c << 16, (v, b, c) counter-clockwise;
                        // padding N | N << 16 (a zero record in the kernel's LDS)
-  const int* vh_hin;   // [DH][N] hinge index (0 in padding)
-  const T* vh_k;       // [DH][N] stencil coefficient of the vertex (0 in padding)
+  const int* vh_hin;   // [N][DH] hinge index (0 in padding)
+  const T* vh_k;       // [N][DH] stencil coefficient of the vertex (0 in padding)
   // Rows of the two Laplacians on their joint pattern (diagonal included),
   // padded to a fixed width DL, slot-major [DL][N]; padding entries have
   // column N and coefficient 0.
@@ -146,6 +147,7 @@ hipError_t launch_adj_end(const ClassSlice<T>& cs, T* xbar, T* vbar, long long s
 
 // Global-step GEMM variants. kind: 0 = FP32, 1 = FP64, 2 = BF16, 3 = FP16.
 hipError_t launch_gemm(int kind, int tile, const GemmArgs& g, hipStream_t st);
+hipError_t gemm_prepare(int kind, int tile, int npad);
 int gemm_num_tiles(int kind);
 void gemm_tile_shape(int tile, int* bm, int* bn);
 

@@ -110,6 +110,39 @@ def test_mixed_precision_refined(prec):
     assert err <= TOL[prec]
 
 
+# every global-step kernel shape (13 tiled shapes, then the column-stationary
+# kernel, reported with tile rows 0), forced through set_config
+GEMM_SHAPES = [(64, 64), (64, 128), (128, 64), (128, 128), (96, 64), (96, 128), (224, 32),
+               (224, 64), (96, 96), (224, 96), (224, 128), (64, 96), (128, 96), (0, 48)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_every_gemm_shape(prec):
+    """17 RBCs (51 columns: one full column-stationary workgroup and a ragged
+    one of 3 columns; ragged tiles for every tiled shape) plus 5 platelets,
+    each kernel shape pinned in turn; 3 steps; 3 cells against the oracle."""
+    import torch
+    from paper_2011_04332_amd import solver
+    s = as_precision(W.precision_sweep(n_rbc=17, n_plt=5, n_steps=3), np.float32)
+    cells = [0, 16, 19]
+    ref = oracle_cells(s, cells)
+    for bm, bn in GEMM_SHAPES:
+        b, pos, vel, f, _ = solver.batch_from_suspension(s, precision=prec)
+        for k in range(len(s.classes)):
+            b.set_config(k, (256, bm, bn, -1))
+        log(f"{prec} gemm shape {bm}x{bn}")
+        for _ in range(s.n_steps):
+            b.step(f, s.dt, s.n_iter)
+        b.sync_status()
+        torch.cuda.synchronize()
+        assert b.config(0)[1:3] == (bm, bn)
+        x = pos.double().cpu().numpy()
+        b.close()
+        err = max_error(s, x, ref)
+        log(f"{prec} gemm shape {bm}x{bn} err {err:.3e}")
+        assert err <= TOL[prec], (bm, bn, err)
+
+
 def test_momentum_and_rest_invariants():
     import torch
     from paper_2011_04332_amd import solver
