@@ -361,26 +361,28 @@ __global__ void __launch_bounds__(256) gemm_lp_kernel(GemmArgs g) {
 // columns (16 cells' three coordinates for RS_NG = 3) for the whole product
 // and keeps them in LDS; the operator, which every workgroup needs whole,
 // streams from L2 (1.7 MB in FP32, 0.9 MB in 16 bits: every XCD's L2 holds
-// it) in 16-row blocks straight into MFMA operand registers, several k-steps
-// ahead of its use. 12288 columns make 256 workgroups, one per CU, so there
-// is no tile quantisation; the four waves split the row blocks, and the row
-// blocks left over after an even split are split by column group.
+// it) in 16-row blocks straight into MFMA operand registers, ahead of its use.
+// 12288 columns make 256 workgroups, one per CU, so there is no tile
+// quantisation; the four waves split the row blocks, and the row blocks left
+// over after an even split are split by column group.
+//
+// LDS layout: k-chunks of 4 (FP32) or 8 (16-bit) values of each column are
+// contiguous 16-byte records, chunk-major: record (q, n) at q * RS_BN + n.
+// The 16 lanes of an MFMA operand fetch read 16 consecutive records (256
+// contiguous bytes), so a wave's fetch touches every bank once per 256 bytes.
 constexpr int RS_NG = 3;
+constexpr int RS_BN = RS_NG * 16;
 constexpr int kNumTilesTiled = 13;  // tile ids below are tiled shapes, this one column-stationary
+constexpr int RS_KS = 24;           // 16-bit: k-steps of 32 held in registers (Npad <= 768)
 
-// LDS column strides: FP32 columns start 4 banks apart (stride = 4 mod 64
-// words), 16-bit columns likewise (stride = 8 mod 128 halves), so the 16
-// lanes that read one k-slice of 16 columns hit 16 disjoint bank quads.
-__host__ __device__ inline int rs_stride_f32(int npad) { return npad + ((4 - npad) % 64 + 64) % 64; }
 __host__ __device__ inline int rs_k32(int npad) { return (npad + 31) / 32 * 32; }
-__host__ __device__ inline int rs_stride_16(int npad) {
-  const int k = rs_k32(npad);
-  return k + ((8 - k) % 128 + 128) % 128;
-}
 
 size_t rs_lds_bytes(int kind, int npad) {
-  if (kind == 0) return sizeof(float) * RS_NG * 16 * (size_t)rs_stride_f32(npad);
-  if (kind >= 2) return 2 * RS_NG * 16 * (size_t)rs_stride_16(npad) + sizeof(float) * RS_NG * 16;
+  if (kind == 0) return sizeof(float) * RS_BN * (size_t)npad;
+  if (kind >= 2) {
+    if (rs_k32(npad) > 32 * RS_KS) return 0;
+    return 2 * RS_BN * (size_t)rs_k32(npad) + sizeof(float) * RS_BN;
+  }
   return 0;
 }
 
@@ -391,8 +393,8 @@ size_t rs_lds_bytes(int kind, int npad) {
 // group the four sub-steps accumulate separately (independent MFMA chains)
 // and are summed at the end.
 template <int NR, int NGU>
-__device__ __forceinline__ void rs_rows_f32(const float* __restrict__ A, const float* Bs, int Kp,
-                                            int Npad, int rb, int g0, float* __restrict__ C, int n0,
+__device__ __forceinline__ void rs_rows_f32(const float* __restrict__ A, const float* Bs, int Npad,
+                                            int rb, int g0, float* __restrict__ C, int n0,
                                             int ncols, int mode, int lane) {
   constexpr int NJ = (NR * NGU == 1) ? 4 : 1;
   constexpr int D = 4;  // prefetch distance in 16-k groups
@@ -407,9 +409,10 @@ __device__ __forceinline__ void rs_rows_f32(const float* __restrict__ A, const f
 #pragma unroll
   for (int r = 0; r < NR; ++r)
     arow[r] = A + (size_t)((rb + r) * 16 + (lane & 15)) * Npad + 4 * (lane >> 4);
+  // record (4 kg + lane/16, g * 16 + lane%16) for k-group kg
   const float* bcol[NGU];
 #pragma unroll
-  for (int u = 0; u < NGU; ++u) bcol[u] = Bs + ((g0 + u) * 16 + (lane & 15)) * Kp + 4 * (lane >> 4);
+  for (int u = 0; u < NGU; ++u) bcol[u] = Bs + 4 * ((lane >> 4) * RS_BN + (g0 + u) * 16 + (lane & 15));
   const int nkg = Npad / 16;
   // Straight-line prefetch: out-of-range prefetches re-read the last group
   // (clamped address, value unused), so the loop body has no branches and the
@@ -420,7 +423,7 @@ __device__ __forceinline__ void rs_rows_f32(const float* __restrict__ A, const f
   auto step = [&](int kg, const float4 (&a)[NR]) {
     float4 b[NGU];
 #pragma unroll
-    for (int u = 0; u < NGU; ++u) b[u] = *reinterpret_cast<const float4*>(bcol[u] + 16 * kg);
+    for (int u = 0; u < NGU; ++u) b[u] = *reinterpret_cast<const float4*>(bcol[u] + 16 * RS_BN * kg);
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -496,29 +499,29 @@ __global__ void __launch_bounds__(256) gemm_rs_f32_kernel(GemmArgs g) {
   const float* __restrict__ A = static_cast<const float*>(g.A);
   const float* __restrict__ B = static_cast<const float*>(g.B);
   float* __restrict__ C = static_cast<float*>(g.C);
-  const int Npad = g.Npad, ncols = g.ncols, Kp = rs_stride_f32(Npad);
-  const int n0 = blockIdx.x * RS_NG * 16;
+  const int Npad = g.Npad, ncols = g.ncols;
+  const int n0 = blockIdx.x * RS_BN;
   const int tid = threadIdx.x;
-  // staging: 8 loads per thread in flight at a time (clamped addresses,
+  // staging, column index fastest (consecutive threads write consecutive
+  // records); 8 loads per thread in flight at a time (clamped addresses,
   // values outside the matrix replaced by zeros, no branches)
-  const int nv = Npad / 4;  // 16-byte vectors per column
-  const int total = RS_NG * 16 * nv;
+  const int total = RS_BN * (Npad / 4);
   for (int i0 = tid; i0 < total; i0 += 256 * 8) {
     float4 v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int i = min(i0 + 256 * u, total - 1);
-      const int n = i / nv, kv = i - n * nv;
-      v[u] = *reinterpret_cast<const float4*>(B + (size_t)min(n0 + n, ncols - 1) * Npad + 4 * kv);
+      const int q = i / RS_BN, n = i - q * RS_BN;
+      v[u] = *reinterpret_cast<const float4*>(B + (size_t)min(n0 + n, ncols - 1) * Npad + 4 * q);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int i = i0 + 256 * u;
       if (i < total) {
-        const int n = i / nv, kv = i - n * nv;
+        const int n = i % RS_BN;
         if (n0 + n >= ncols) v[u] = float4{0.f, 0.f, 0.f, 0.f};
-        *reinterpret_cast<float4*>(rs_lds + n * Kp + 4 * kv) = v[u];
+        *reinterpret_cast<float4*>(rs_lds + 4 * i) = v[u];
       }
     }
   }
@@ -528,111 +531,109 @@ __global__ void __launch_bounds__(256) gemm_rs_f32_kernel(GemmArgs g) {
   const int wave = tid >> 6, lane = tid & 63;
   const int nrb = Npad / 16, full = nrb & ~7;
   for (int rb = 2 * wave; rb < full; rb += 8)
-    rs_rows_f32<2, RS_NG>(A, rs_lds, Kp, Npad, rb, 0, C, n0, ncols, g.mode, lane);
+    rs_rows_f32<2, RS_NG>(A, rs_lds, Npad, rb, 0, C, n0, ncols, g.mode, lane);
   for (int u = wave; u < (nrb - full) * RS_NG; u += 4)
-    rs_rows_f32<1, 1>(A, rs_lds, Kp, Npad, full + u / RS_NG, u % RS_NG, C, n0, ncols, g.mode, lane);
+    rs_rows_f32<1, 1>(A, rs_lds, Npad, full + u / RS_NG, u % RS_NG, C, n0, ncols, g.mode, lane);
 }
 
 // 16-bit version: the split operator Bt (16-bit, [Npad][Npad]) against the
 // columns converted once into LDS (each scaled by a power of two as in the
-// tiled kernel), k-steps of 32 (16x16x32 MFMA), k beyond Npad zero. The
+// tiled kernel), k-steps of 32 (16x16x32 MFMA), k beyond Npad zero. A wave
+// holds a whole 16-row block of the operator in registers (Npad <= 768) and
+// fetches the next row block's while it multiplies the current one. The
 // epilogue applies C = hm (B + beta / s_n Bt B) with B re-read in FP32.
 template <typename L, int NGU>
-__device__ __forceinline__ void rs_rows_lp(const L* __restrict__ A, const L* Bs, int Kp, int Npad,
-                                           int rb, int g0, const float* __restrict__ B,
-                                           float* __restrict__ C, const float* sc, int n0,
-                                           int ncols, const GemmArgs& g, int lane) {
+struct RsLpRows {
   typedef typename Mfma32<L>::vec_t vec_t;
-  constexpr int NJ = NGU == 1 ? 2 : 1;
-  constexpr int D = 12;  // prefetch distance in 32-k steps
-  floatx4 acc[NGU][NJ];
+  // register image of one row block: k-step ks of lane l covers
+  // k = 32 ks + 8 (l/16) .. + 7 of row 16 rb + l%16
+  static __device__ __forceinline__ void load(const L* __restrict__ A, int Npad, int rb, int lane,
+                                              vec_t (&dst)[RS_KS]) {
+    const L* __restrict__ arow = A + (size_t)(rb * 16 + (lane & 15)) * Npad;
+    const int kl = 8 * (lane >> 4);
 #pragma unroll
-  for (int u = 0; u < NGU; ++u)
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) acc[u][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int kl = 8 * (lane >> 4);
-  const L* __restrict__ arow = A + (size_t)(rb * 16 + (lane & 15)) * Npad + kl;
-  const L* bcol[NGU];
-#pragma unroll
-  for (int u = 0; u < NGU; ++u) bcol[u] = Bs + ((g0 + u) * 16 + (lane & 15)) * Kp + kl;
-  const int nks = rs_k32(Npad) / 32;
-  // Straight-line prefetch as in the FP32 version; k >= Npad (the last step
-  // when Npad is an odd multiple of 16) reads a clamped, valid address and
-  // is replaced by zeros.
-  auto load_a = [&](int ks) {
-    const int k = 32 * min(ks, nks - 1) + kl;
-    vec_t a = *reinterpret_cast<const vec_t*>(arow - kl + min(k, Npad - 8));
-    if (k >= Npad) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) a[e] = L(0.0f);
-    }
-    return a;
-  };
-  auto step = [&](int ks, const vec_t& a) {
+    for (int ks = 0; ks < RS_KS; ++ks)
+      dst[ks] = *reinterpret_cast<const vec_t*>(arow + min(32 * ks + kl, Npad - 8));
+  }
+  static __device__ __forceinline__ void run(const vec_t (&a_in)[RS_KS], const L* Bs, int Npad,
+                                             int rb, int g0, const float* __restrict__ B,
+                                             float* __restrict__ C, const float* sc, int n0,
+                                             int ncols, const GemmArgs& g, int lane) {
+    constexpr int NJ = NGU == 1 ? 2 : 1;
+    const int kl = 8 * (lane >> 4);
+    const int nks = rs_k32(Npad) / 32;
+    // the FP32 columns the epilogue needs (clamped column index: columns
+    // past the last are never stored)
+    float4 bv[NGU];
+    const int m_ep = rb * 16 + 4 * (lane >> 4);
 #pragma unroll
     for (int u = 0; u < NGU; ++u) {
-      const vec_t b = *reinterpret_cast<const vec_t*>(bcol[u] + 32 * ks);
-      acc[u][ks % NJ] = Mfma32<L>::run(a, b, acc[u][ks % NJ]);
+      const int n = min(n0 + (g0 + u) * 16 + (lane & 15), ncols - 1);
+      bv[u] = *reinterpret_cast<const float4*>(B + (size_t)n * Npad + m_ep);
     }
-  };
-  vec_t cur[D], nxt[D];
+    floatx4 acc[NGU][NJ];
 #pragma unroll
-  for (int i = 0; i < D; ++i) cur[i] = load_a(i);
-  int ks = 0;
-  for (; ks + D <= nks; ks += D) {
+    for (int u = 0; u < NGU; ++u)
 #pragma unroll
-    for (int i = 0; i < D; ++i) nxt[i] = load_a(ks + D + i);
-    __builtin_amdgcn_sched_barrier(0);
+      for (int j = 0; j < NJ; ++j) acc[u][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const L* bcol = Bs + 8 * ((lane >> 4) * RS_BN + g0 * 16 + (lane & 15));
 #pragma unroll
-    for (int i = 0; i < D; ++i) step(ks + i, cur[i]);
+    for (int ks = 0; ks < RS_KS; ++ks) {
+      if (ks < nks) {
+        vec_t a = a_in[ks];
+        if (32 * ks + kl >= Npad) {
 #pragma unroll
-    for (int i = 0; i < D; ++i) cur[i] = nxt[i];
-  }
+          for (int e = 0; e < 8; ++e) a[e] = L(0.0f);
+        }
 #pragma unroll
-  for (int i = 0; i < D; ++i)
-    if (i < nks - ks) step(ks + i, cur[i]);
-  const float hm = (float)g.hm, beta = (float)g.beta;
+        for (int u = 0; u < NGU; ++u) {
+          const vec_t b = *reinterpret_cast<const vec_t*>(bcol + 8 * (4 * RS_BN * ks + 16 * u));
+          acc[u][ks % NJ] = Mfma32<L>::run(a, b, acc[u][ks % NJ]);
+        }
+      }
+    }
+    const float hm = (float)g.hm, beta = (float)g.beta;
 #pragma unroll
-  for (int u = 0; u < NGU; ++u) {
+    for (int u = 0; u < NGU; ++u) {
 #pragma unroll
-    for (int j = 1; j < NJ; ++j) acc[u][0] += acc[u][j];
-    const int nl = (g0 + u) * 16 + (lane & 15);
-    const int n = n0 + nl;
-    if (n >= ncols) continue;
-    const int m = rb * 16 + 4 * (lane >> 4);
-    const float unscale = beta / sc[nl];
-    const float4 bv = *reinterpret_cast<const float4*>(B + (size_t)n * Npad + m);
-    float4* c = reinterpret_cast<float4*>(C + (size_t)n * Npad + m);
-    float4 v;
-    v.x = hm * (bv.x + unscale * acc[u][0][0]);
-    v.y = hm * (bv.y + unscale * acc[u][0][1]);
-    v.z = hm * (bv.z + unscale * acc[u][0][2]);
-    v.w = hm * (bv.w + unscale * acc[u][0][3]);
-    if (g.mode == EPI_SPLIT_ADD) {
-      float4 o = *c;
-      o.x += v.x;
-      o.y += v.y;
-      o.z += v.z;
-      o.w += v.w;
-      *c = o;
-    } else {
-      *c = v;
+      for (int j = 1; j < NJ; ++j) acc[u][0] += acc[u][j];
+      const int nl = (g0 + u) * 16 + (lane & 15);
+      const int n = n0 + nl;
+      if (n >= ncols) continue;
+      const float unscale = beta / sc[nl];
+      float4* c = reinterpret_cast<float4*>(C + (size_t)n * Npad + m_ep);
+      float4 v;
+      v.x = hm * (bv[u].x + unscale * acc[u][0][0]);
+      v.y = hm * (bv[u].y + unscale * acc[u][0][1]);
+      v.z = hm * (bv[u].z + unscale * acc[u][0][2]);
+      v.w = hm * (bv[u].w + unscale * acc[u][0][3]);
+      if (g.mode == EPI_SPLIT_ADD) {
+        float4 o = *c;
+        o.x += v.x;
+        o.y += v.y;
+        o.z += v.z;
+        o.w += v.w;
+        *c = o;
+      } else {
+        *c = v;
+      }
     }
   }
-}
+};
 
 template <typename L>
 __global__ void __launch_bounds__(256) gemm_rs_lp_kernel(GemmArgs g) {
+  typedef typename Mfma32<L>::vec_t vec_t;
   extern __shared__ float rs_lds_lp[];
   const L* __restrict__ A = static_cast<const L*>(g.A);
   const float* __restrict__ B = static_cast<const float*>(g.B);
   float* __restrict__ C = static_cast<float*>(g.C);
-  const int Npad = g.Npad, ncols = g.ncols, Kp = rs_stride_16(Npad), K32 = rs_k32(Npad);
-  const int n0 = blockIdx.x * RS_NG * 16;
+  const int Npad = g.Npad, ncols = g.ncols, K32 = rs_k32(Npad);
+  const int n0 = blockIdx.x * RS_BN;
   const int tid = threadIdx.x;
-  float* sc = rs_lds_lp;                                      // [RS_NG * 16] column scales
-  L* Bs = reinterpret_cast<L*>(rs_lds_lp + RS_NG * 16);       // [RS_NG * 16][Kp]
-  for (int j = tid; j < RS_NG * 16; j += 256) {
+  float* sc = rs_lds_lp;                               // [RS_BN] column scales
+  L* Bs = reinterpret_cast<L*>(rs_lds_lp + RS_BN);     // records (q, n), 8 values each
+  for (int j = tid; j < RS_BN; j += 256) {
     float s = 1.0f;
     const int n = n0 + j;
     if (g.colscale && n < ncols) {
@@ -642,17 +643,16 @@ __global__ void __launch_bounds__(256) gemm_rs_lp_kernel(GemmArgs g) {
     sc[j] = s;
   }
   __syncthreads();
-  // staging: 8 vector pairs per thread in flight at a time (clamped
-  // addresses, values outside the matrix replaced by zeros, no branches)
-  const int nv = K32 / 8;  // 8-element vectors per column
-  const int total = RS_NG * 16 * nv;
+  // staging, column index fastest; 8 vector pairs per thread in flight at a
+  // time (clamped addresses, values outside the matrix replaced by zeros)
+  const int total = RS_BN * (K32 / 8);
   for (int i0 = tid; i0 < total; i0 += 256 * 8) {
     float4 lo[8], hi[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int i = min(i0 + 256 * u, total - 1);
-      const int n = i / nv, kv = i - n * nv;
-      const float* src = B + (size_t)min(n0 + n, ncols - 1) * Npad + min(8 * kv, Npad - 8);
+      const int q = i / RS_BN, n = i - q * RS_BN;
+      const float* src = B + (size_t)min(n0 + n, ncols - 1) * Npad + min(8 * q, Npad - 8);
       lo[u] = *reinterpret_cast<const float4*>(src);
       hi[u] = *reinterpret_cast<const float4*>(src + 4);
     }
@@ -661,11 +661,10 @@ __global__ void __launch_bounds__(256) gemm_rs_lp_kernel(GemmArgs g) {
     for (int u = 0; u < 8; ++u) {
       const int i = i0 + 256 * u;
       if (i < total) {
-        const int n = i / nv, kv = i - n * nv;
-        const int k = 8 * kv;
-        const bool in = n0 + n < ncols && k < Npad;
+        const int q = i / RS_BN, n = i - q * RS_BN;
+        const bool in = n0 + n < ncols && 8 * q < Npad;
         const float s = in ? sc[n] : 0.0f;
-        typename Mfma32<L>::vec_t v;
+        vec_t v;
         v[0] = L(lo[u].x * s);
         v[1] = L(lo[u].y * s);
         v[2] = L(lo[u].z * s);
@@ -674,17 +673,31 @@ __global__ void __launch_bounds__(256) gemm_rs_lp_kernel(GemmArgs g) {
         v[5] = L(hi[u].y * s);
         v[6] = L(hi[u].z * s);
         v[7] = L(hi[u].w * s);
-        *reinterpret_cast<typename Mfma32<L>::vec_t*>(Bs + n * Kp + k) = v;
+        *reinterpret_cast<vec_t*>(Bs + 8 * i) = v;
       }
     }
   }
   __syncthreads();
   const int wave = tid >> 6, lane = tid & 63;
   const int nrb = Npad / 16, full = nrb & ~3;
-  for (int rb = wave; rb < full; rb += 4)
-    rs_rows_lp<L, RS_NG>(A, Bs, Kp, Npad, rb, 0, B, C, sc, n0, ncols, g, lane);
-  for (int u = wave; u < (nrb - full) * RS_NG; u += 4)
-    rs_rows_lp<L, 1>(A, Bs, Kp, Npad, full + u / RS_NG, u % RS_NG, B, C, sc, n0, ncols, g, lane);
+  // full row blocks: the next row block's operator rows are in flight while
+  // the current one is multiplied (two register images)
+  {
+    vec_t cur[RS_KS], nxt[RS_KS];
+    if (wave < full) RsLpRows<L, RS_NG>::load(A, Npad, wave, lane, cur);
+    for (int rb = wave; rb < full; rb += 4) {
+      if (rb + 4 < full) RsLpRows<L, RS_NG>::load(A, Npad, rb + 4, lane, nxt);
+      __builtin_amdgcn_sched_barrier(0);
+      RsLpRows<L, RS_NG>::run(cur, Bs, Npad, rb, 0, B, C, sc, n0, ncols, g, lane);
+#pragma unroll
+      for (int ks = 0; ks < RS_KS; ++ks) cur[ks] = nxt[ks];
+    }
+  }
+  for (int u = wave; u < (nrb - full) * RS_NG; u += 4) {
+    vec_t a[RS_KS];
+    RsLpRows<L, 1>::load(A, Npad, full + u / RS_NG, lane, a);
+    RsLpRows<L, 1>::run(a, Bs, Npad, full + u / RS_NG, u % RS_NG, B, C, sc, n0, ncols, g, lane);
+  }
 }
 
 static const void* rs_kernel(int kind) {

@@ -191,11 +191,12 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
     }
     __syncthreads();
     const bool whole = (nt == F);  // one chunk: every entry is in range
+    // two fused multiply-adds per component
     auto tri_add = [&](int j, int t, V2<T> g2) {
       const T* w = work + 6 * t;
-      acc[j][0] += g2.x * w[0] + g2.y * w[1];
-      acc[j][1] += g2.x * w[2] + g2.y * w[3];
-      acc[j][2] += g2.x * w[4] + g2.y * w[5];
+      acc[j][0] = fma(g2.y, w[1], fma(g2.x, w[0], acc[j][0]));
+      acc[j][1] = fma(g2.y, w[3], fma(g2.x, w[2], acc[j][1]));
+      acc[j][2] = fma(g2.y, w[5], fma(g2.x, w[4], acc[j][2]));
     };
     if constexpr (KT > 0) {
       if (whole) {
@@ -205,10 +206,12 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
         V2<T> gg[2][KT];
         auto fetch = [&](int j, int set) {
           const int v = min(tid + j * BLOCK, N - 1);  // clamped: always a valid row
+          const int* __restrict__ tp = cv.vt_tri + v * KT;
+          const V2<T>* __restrict__ gp = reinterpret_cast<const V2<T>*>(cv.vt_g) + v * KT;
 #pragma unroll
           for (int u = 0; u < KT; ++u) {
-            tt[set][u] = cv.vt_tri[v * KT + u];
-            gg[set][u] = reinterpret_cast<const V2<T>*>(cv.vt_g)[v * KT + u];
+            tt[set][u] = tp[u];
+            gg[set][u] = gp[u];
           }
         };
         fetch(0, 0);
@@ -308,10 +311,12 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
         T kk[2][KH];
         auto fetch = [&](int j, int set) {
           const int v = min(tid + j * BLOCK, N - 1);
+          const int* __restrict__ hp = cv.vh_hin + v * KH;
+          const T* __restrict__ kp = cv.vh_k + v * KH;
 #pragma unroll
           for (int u = 0; u < KH; ++u) {
-            hh[set][u] = cv.vh_hin[v * KH + u];
-            kk[set][u] = cv.vh_k[v * KH + u];
+            hh[set][u] = hp[u];
+            kk[set][u] = kp[u];
           }
         };
         fetch(0, 0);

@@ -4,6 +4,8 @@
 // Layouts: the caller's state is SoA [3][sumN]; the solver's column buffers
 // hold one column per (cell, coordinate) of Npad entries (rows >= N are zero),
 // so that the global step is a plain GEMM over 3 * cells columns.
+#include <algorithm>
+
 #include "device_utils.h"
 #include "npfem_internal.h"
 
@@ -67,33 +69,36 @@ __global__ void __launch_bounds__(256) update_kernel(ClassSlice<T> cs, T* __rest
 
 // Refinement residual res = r - A_c delta for each cell, with the per-cell
 // system A_c = (m/h^2 + w_v) I + (w_s + w_a) L_tri + w_b L_bend (fixed-width
-// rows of the two Laplacians). The cell's delta is staged in LDS (three
-// arrays of N + 1 values, the last one 0 for padding entries); products
-// accumulate in FP64. One workgroup per cell.
+// rows of the two Laplacians, shared by the class). One workgroup per cell
+// with one thread per row (up to 1024 rows at a time), so that a wave has few
+// memory round trips in sequence and many waves share each SIMD. The cell's
+// delta is staged in LDS (N + 1 values per coordinate, the last one 0 for
+// padding entries); products accumulate in FP64. colmax: per column max
+// |res| (FP16 scaling): wave maxima, then LDS atomic max on the bit patterns
+// of the non-negative floats.
 template <typename T>
-__global__ void __launch_bounds__(256) residual_kernel(ClassSlice<T> cs, const T* __restrict__ rhs,
-                                                       const T* __restrict__ delta,
-                                                       T* __restrict__ res,
-                                                       const T* __restrict__ weights,
-                                                       float* __restrict__ colmax, double h) {
+__global__ void __launch_bounds__(1024) residual_kernel(ClassSlice<T> cs, const T* __restrict__ rhs,
+                                                        const T* __restrict__ delta,
+                                                        T* __restrict__ res,
+                                                        const T* __restrict__ weights,
+                                                        float* __restrict__ colmax, double h) {
   extern __shared__ double smem_res[];
-  float* redf = reinterpret_cast<float*>(smem_res);  // 4 floats
-  T* sd = reinterpret_cast<T*>(smem_res + 2);        // [3][N + 1]
-  const int lc = blockIdx.x;
+  unsigned* cmx = reinterpret_cast<unsigned*>(smem_res);  // [3]
+  T* sd = reinterpret_cast<T*>(smem_res + 2);             // [3][N + 1]
   const int N = cs.cv.N, Npad = cs.cv.Npad, DL = cs.cv.DL;
+  const int lc = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   const long long cb = cs.elem0 + 3LL * lc * Npad;
   const int* __restrict__ lcol = cs.cv.lap_col;
   const T* __restrict__ lt = cs.cv.lap_t;
   const T* __restrict__ lb = cs.cv.lap_b;
-  T* sx = sd;
-  T* sy = sd + (N + 1);
-  T* sz = sd + 2 * (N + 1);
-  for (int v = threadIdx.x; v <= N; v += blockDim.x) {
-    const bool in = v < N;
-    sx[v] = in ? delta[cb + v] : T(0);
-    sy[v] = in ? delta[cb + Npad + v] : T(0);
-    sz[v] = in ? delta[cb + 2 * Npad + v] : T(0);
+  for (int v = tid; v <= N; v += nt) {
+    const int vc = min(v, N - 1);
+    const T dx = delta[cb + vc], dy = delta[cb + Npad + vc], dz = delta[cb + 2 * Npad + vc];
+    sd[v] = v < N ? dx : T(0);
+    sd[(N + 1) + v] = v < N ? dy : T(0);
+    sd[2 * (N + 1) + v] = v < N ? dz : T(0);
   }
+  if (tid < 3) cmx[tid] = 0u;
   __syncthreads();
   const int cell = cs.cell0 + lc;
   double w[4];
@@ -102,33 +107,33 @@ __global__ void __launch_bounds__(256) residual_kernel(ClassSlice<T> cs, const T
   const double diag = (double)cs.mass / (h * h) + w[3];
   const double wt = w[0] + w[1], wb = w[2];
   float cm[3] = {0.f, 0.f, 0.f};
-  for (int v = threadIdx.x; v < Npad; v += blockDim.x) {
+  for (int v = tid; v < Npad; v += nt) {
     double a0 = 0, a1 = 0, a2 = 0;
     if (v < N) {
       const T r0 = rhs[cb + v], r1 = rhs[cb + Npad + v], r2 = rhs[cb + 2 * Npad + v];
-      a0 = diag * (double)sx[v];
-      a1 = diag * (double)sy[v];
-      a2 = diag * (double)sz[v];
-      // row entries fetched 8 at a time, one memory round trip per batch
-      // (the index past the last slot is clamped and its weight zeroed)
+      a0 = diag * (double)sd[v];
+      a1 = diag * (double)sd[(N + 1) + v];
+      a2 = diag * (double)sd[2 * (N + 1) + v];
+      // row entries fetched 8 at a time (the slots past the last clamped,
+      // their weight zeroed)
       for (int k0 = 0; k0 < DL; k0 += 8) {
         int jj[8];
-        T ct[8], cb[8];
+        T ct[8], cbv[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int e = min(k0 + u, DL - 1) * N + v;
           jj[u] = lcol[e];
           ct[u] = lt[e];
-          cb[u] = lb[e];
+          cbv[u] = lb[e];
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          const double c = k0 + u < DL ? wt * (double)ct[u] + wb * (double)cb[u] : 0.0;
+          const double c = k0 + u < DL ? wt * (double)ct[u] + wb * (double)cbv[u] : 0.0;
           const int j = jj[u];
-          a0 += c * (double)sx[j];
-          a1 += c * (double)sy[j];
-          a2 += c * (double)sz[j];
+          a0 += c * (double)sd[j];
+          a1 += c * (double)sd[(N + 1) + j];
+          a2 += c * (double)sd[2 * (N + 1) + j];
         }
       }
       a0 = (double)r0 - a0;
@@ -143,11 +148,14 @@ __global__ void __launch_bounds__(256) residual_kernel(ClassSlice<T> cs, const T
     cm[2] = fmaxf(cm[2], fabsf((float)a2));
   }
   if (colmax) {
+    // wave maxima first, then one LDS atomic per wave and coordinate
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const float mx = block_max(cm[d], redf);
-      if (threadIdx.x == 0) colmax[cs.col0 + 3LL * lc + d] = mx;
+      const float mx = wave_max(cm[d]);
+      if ((tid & (kWave - 1)) == 0) atomicMax(&cmx[d], __float_as_uint(mx));
     }
+    __syncthreads();
+    if (tid < 3) colmax[cs.col0 + 3LL * lc + tid] = __uint_as_float(cmx[tid]);
   }
 }
 
@@ -199,8 +207,11 @@ template <typename T>
 hipError_t launch_residual(const ClassSlice<T>& cs, const T* rhs, const T* delta, T* res,
                            const T* weights, float* colmax, double h, hipStream_t st) {
   if (cs.n_cells == 0) return hipSuccess;
-  const size_t smem = 2 * sizeof(double) + sizeof(T) * 3 * ((size_t)cs.cv.N + 1);
-  hipLaunchKernelGGL(residual_kernel<T>, dim3(cs.n_cells), dim3(256), smem, st, cs, rhs, delta,
+  const int N = cs.cv.N;
+  const size_t smem = 2 * sizeof(double) + sizeof(T) * 3 * ((size_t)N + 1);
+  if (smem > 64 * 1024) return hipErrorInvalidValue;
+  const int block = std::min(1024, (cs.cv.Npad + 63) / 64 * 64);
+  hipLaunchKernelGGL(residual_kernel<T>, dim3(cs.n_cells), dim3(block), smem, st, cs, rhs, delta,
                      res, weights, colmax, h);
   return hipGetLastError();
 }
