@@ -139,7 +139,8 @@ def kernel_source_digest():
     import hashlib
     h = hashlib.sha256()
     root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2011_04332_amd", "csrc")
-    for name in ("kernels_local.hip", "kernels_gemm.hip", "device_utils.h", "npfem_internal.h"):
+    for name in ("kernels_local.hip", "local_common.h", "kernels_gemm.hip", "device_utils.h",
+                 "npfem_internal.h"):
         with open(os.path.join(root, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -174,6 +175,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--pin-config", default="",
+                    help="local block,tile m,tile n,sweeps for every class (skips the autotuner); "
+                         "profiling runs use it to launch exactly the configuration the timed run chose")
     ap.add_argument("--compare-precision", default="fp16", choices=["none", "bf16", "fp16"],
                     help="also time the workload with this 16-bit global step (FP32 runs only)")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -207,8 +211,12 @@ def main():
     print(f"[bench] workload {a.workload}: {desc}; {a.precision}; steps {a.steps} warmup {a.warmup}",
           file=sys.stderr, flush=True)
 
-    b, pos, vel, f, meshes = solver.batch_from_suspension(s, precision=a.precision,
-                                                          autotune=not a.no_autotune)
+    pinned = [int(v) for v in a.pin_config.split(",")] if a.pin_config else None
+    b, pos, vel, f, meshes = solver.batch_from_suspension(
+        s, precision=a.precision, autotune=not (a.no_autotune or pinned))
+    if pinned:
+        for k in range(len(s.classes)):
+            b.set_config(k, pinned)
     x_init, v_init = pos.clone(), vel.clone()
     for _ in range(max(1, a.warmup)):
         b.step(f, dt, n_iter)
