@@ -180,6 +180,9 @@ def main():
                          "profiling runs use it to launch exactly the configuration the timed run chose")
     ap.add_argument("--compare-precision", default="fp16", choices=["none", "bf16", "fp16"],
                     help="also time the workload with this 16-bit global step (FP32 runs only)")
+    ap.add_argument("--mixed-sweeps", type=int, default=-1,
+                    help="correction sweeps of the 16-bit comparison run (-1: the library's "
+                         "automatic count)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the forward + backward timing of the differentiation workload")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -303,7 +306,8 @@ def main():
         vel.copy_(v_init)
         bm = solver.Batch(meshes, s.cell_class, pos, vel,
                           cell_weights=None if s.uniform_weights() else s.weights,
-                          precision=a.compare_precision, autotune=not a.no_autotune)
+                          precision=a.compare_precision, autotune=not a.no_autotune,
+                          n_refine=a.mixed_sweeps)
         for _ in range(cpu_steps):
             bm.step(f, dt, n_iter)
         bm.sync_status()

@@ -209,6 +209,17 @@ struct Mfma32<_Float16> {
   }
 };
 
+// Power-of-two scale of column n from its max |.| (1 without maxima). In the
+// accumulating mode a zero maximum marks a column that needs no correction
+// (the residual step found its error below the state's rounding): scale 0,
+// and the column is neither read nor written.
+__device__ __forceinline__ float lp_col_scale(const GemmArgs& g, int n) {
+  if (!g.colscale || n >= g.ncols) return 1.0f;
+  const float mx = g.colscale[n];
+  if (mx > 0.0f && isfinite(mx)) return exp2f(-ceilf(log2f(mx)));
+  return (g.mode == EPI_SPLIT_ADD && mx == 0.0f) ? 0.0f : 1.0f;
+}
+
 // C = hm * (B + beta * Bt * B)   (SPLIT_SET) or C += that (SPLIT_ADD).
 // B columns are FP32 in memory; each column is multiplied by a power of two
 // (from its max |.|) before rounding to the 16-bit type, and divided back in
@@ -237,16 +248,13 @@ __global__ void __launch_bounds__(256) gemm_lp_kernel(GemmArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
 
+  bool live = false;
   for (int j = tid; j < BN; j += 256) {
-    float s = 1.0f;
-    const int n = n0 + j;
-    if (g.colscale && n < ncols) {
-      const float mx = g.colscale[n];
-      if (mx > 0.0f && isfinite(mx)) s = exp2f(-ceilf(log2f(mx)));
-    }
+    const float s = lp_col_scale(g, n0 + j);
     sc_in[j] = s;
+    live = live || (s != 0.0f && n0 + j < ncols);
   }
-  __syncthreads();
+  if (!__syncthreads_or(live)) return;  // no column of the tile needs work
 
   vec_t ra[NA], rb[NB];
   auto load_tiles = [&](int k0) {
@@ -340,7 +348,7 @@ __global__ void __launch_bounds__(256) gemm_lp_kernel(GemmArgs g) {
     for (int j = 0; j < TN; ++j) {
       const int nn = wn * WN + j * 16 + (lane & 15);
       const int n = n0 + nn;
-      if (n >= ncols) continue;
+      if (n >= ncols || sc_in[nn] == 0.0f) continue;
       const float unscale = beta / sc_in[nn];
       const float* bcol = B + (size_t)n * Npad + m;
       float* c = C + (size_t)n * Npad + m;
@@ -373,18 +381,8 @@ __global__ void __launch_bounds__(256) gemm_lp_kernel(GemmArgs g) {
 constexpr int RS_NG = 3;
 constexpr int RS_BN = RS_NG * 16;
 constexpr int kNumTilesTiled = 13;  // tile ids below are tiled shapes, this one column-stationary
-constexpr int RS_KS = 24;           // 16-bit: k-steps of 32 held in registers (Npad <= 768)
 
 __host__ __device__ inline int rs_k32(int npad) { return (npad + 31) / 32 * 32; }
-
-size_t rs_lds_bytes(int kind, int npad) {
-  if (kind == 0) return sizeof(float) * RS_BN * (size_t)npad;
-  if (kind >= 2) {
-    if (rs_k32(npad) > 32 * RS_KS) return 0;
-    return 2 * RS_BN * (size_t)rs_k32(npad) + sizeof(float) * RS_BN;
-  }
-  return 0;
-}
 
 // Rows [16 rb, 16 (rb + NR)) of column groups [g0, g0 + NGU) (FP32). Lane l
 // feeds the MFMA k-index l/16 with k = k0 + 4 (l/16) + j at sub-step j, for A
@@ -527,125 +525,168 @@ __global__ void __launch_bounds__(256) gemm_rs_f32_kernel(GemmArgs g) {
   }
   __syncthreads();
   // row blocks in pairs, the pairs split evenly over the four waves; the
-  // remaining row blocks one column group at a time
+  // remaining row blocks one column group at a time. Every workgroup needs
+  // the whole operator: workgroups on one XCD (consecutive ones sit on
+  // different XCDs) start at different row pairs, so that their concurrent
+  // requests spread over the L2 channels instead of queueing on the same
+  // lines.
   const int wave = tid >> 6, lane = tid & 63;
   const int nrb = Npad / 16, full = nrb & ~7;
-  for (int rb = 2 * wave; rb < full; rb += 8)
+  const int rot = full > 0 ? 2 * ((blockIdx.x / 8) % (full / 2)) : 0;
+  for (int i = 2 * wave; i < full; i += 8) {
+    const int rb = i + rot < full ? i + rot : i + rot - full;
     rs_rows_f32<2, RS_NG>(A, rs_lds, Npad, rb, 0, C, n0, ncols, g.mode, lane);
+  }
   for (int u = wave; u < (nrb - full) * RS_NG; u += 4)
     rs_rows_f32<1, 1>(A, rs_lds, Npad, full + u / RS_NG, u % RS_NG, C, n0, ncols, g.mode, lane);
 }
 
 // 16-bit version: the split operator Bt (16-bit, [Npad][Npad]) against the
 // columns converted once into LDS (each scaled by a power of two as in the
-// tiled kernel), k-steps of 32 (16x16x32 MFMA), k beyond Npad zero. A wave
-// holds a whole 16-row block of the operator in registers (Npad <= 768) and
-// fetches the next row block's while it multiplies the current one. The
-// epilogue applies C = hm (B + beta / s_n Bt B) with B re-read in FP32.
-template <typename L, int NGU>
+// tiled kernel), k-steps of 32 (16x16x32 MFMA). The number of k-steps NKS is
+// a template parameter (Npad rounded up to 32, then to a multiple of
+// RS_KS_STEP k-steps), so that a row block's multiply is one straight-line
+// block: the accumulators stay in place and the LDS reads run ahead of the
+// MFMAs. k at or beyond Npad: the LDS records hold zeros, and the operator
+// values there (read from a clamped, in-row address) multiply those zeros.
+// A wave holds a whole 16-row block of the operator in registers and
+// fetches the next one into a second register image while it multiplies
+// (the two images alternate, nothing is copied). The epilogue applies
+// C = hm (B + beta / s_n Bt B) (or adds it to C) with B re-read in FP32;
+// those loads, and the C loads of the accumulating mode, are issued before
+// the next row block's operator loads so that the epilogue waits for them
+// alone.
+constexpr int RS_KS_STEP = 3;
+constexpr int RS_KS_MAX = 24;  // Npad <= 768
+
+__host__ __device__ inline int rs_nks(int npad) {
+  const int k = rs_k32(npad) / 32;
+  return (k + RS_KS_STEP - 1) / RS_KS_STEP * RS_KS_STEP;
+}
+
+size_t rs_lds_bytes(int kind, int npad) {
+  if (kind == 0) return sizeof(float) * RS_BN * (size_t)npad;
+  if (kind >= 2) {
+    if (rs_nks(npad) > RS_KS_MAX) return 0;
+    return 2 * RS_BN * 32 * (size_t)rs_nks(npad) + sizeof(float) * RS_BN;
+  }
+  return 0;
+}
+
+template <typename L, int NKS, int NGU>
 struct RsLpRows {
   typedef typename Mfma32<L>::vec_t vec_t;
+  // epilogue inputs of one row block and NGU column groups
+  struct Epi {
+    float4 b[NGU];
+    float4 c[NGU];
+  };
   // register image of one row block: k-step ks of lane l covers
   // k = 32 ks + 8 (l/16) .. + 7 of row 16 rb + l%16
   static __device__ __forceinline__ void load(const L* __restrict__ A, int Npad, int rb, int lane,
-                                              vec_t (&dst)[RS_KS]) {
+                                              vec_t (&dst)[NKS]) {
     const L* __restrict__ arow = A + (size_t)(rb * 16 + (lane & 15)) * Npad;
     const int kl = 8 * (lane >> 4);
 #pragma unroll
-    for (int ks = 0; ks < RS_KS; ++ks)
+    for (int ks = 0; ks < NKS; ++ks)
       dst[ks] = *reinterpret_cast<const vec_t*>(arow + min(32 * ks + kl, Npad - 8));
   }
-  static __device__ __forceinline__ void run(const vec_t (&a_in)[RS_KS], const L* Bs, int Npad,
-                                             int rb, int g0, const float* __restrict__ B,
-                                             float* __restrict__ C, const float* sc, int n0,
-                                             int ncols, const GemmArgs& g, int lane) {
-    constexpr int NJ = NGU == 1 ? 2 : 1;
-    const int kl = 8 * (lane >> 4);
-    const int nks = rs_k32(Npad) / 32;
-    // the FP32 columns the epilogue needs (clamped column index: columns
-    // past the last are never stored)
-    float4 bv[NGU];
+  // lane l holds rows 16 rb + 4 (l/16) .. + 3 of column group g0 + u, column
+  // l%16 (clamped column index: columns past the last are never stored)
+  static __device__ __forceinline__ void load_epi(const float* __restrict__ B,
+                                                  const float* __restrict__ C, int Npad, int rb,
+                                                  int g0, int n0, int ncols, bool add, int lane,
+                                                  Epi& e) {
     const int m_ep = rb * 16 + 4 * (lane >> 4);
 #pragma unroll
     for (int u = 0; u < NGU; ++u) {
       const int n = min(n0 + (g0 + u) * 16 + (lane & 15), ncols - 1);
-      bv[u] = *reinterpret_cast<const float4*>(B + (size_t)n * Npad + m_ep);
+      e.b[u] = *reinterpret_cast<const float4*>(B + (size_t)n * Npad + m_ep);
+      e.c[u] = add ? *reinterpret_cast<const float4*>(C + (size_t)n * Npad + m_ep)
+                   : float4{0.f, 0.f, 0.f, 0.f};
     }
+  }
+  static __device__ __forceinline__ void run(const vec_t (&a)[NKS], const L* Bs, int Npad, int rb,
+                                             int g0, float* __restrict__ C, const float* sc,
+                                             int n0, int ncols, float hm, float beta, bool add,
+                                             int lane, const Epi& e) {
+    // independent accumulation chains when a single column group is done
+    constexpr int NJ = NGU == 1 ? RS_KS_STEP : 1;
     floatx4 acc[NGU][NJ];
 #pragma unroll
     for (int u = 0; u < NGU; ++u)
 #pragma unroll
       for (int j = 0; j < NJ; ++j) acc[u][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     const L* bcol = Bs + 8 * ((lane >> 4) * RS_BN + g0 * 16 + (lane & 15));
+    // LDS fragments PF k-steps ahead of their MFMAs (scheduling barriers keep
+    // the compiler from folding the reads back next to their use)
+    constexpr int PF = 2;
+    vec_t bq[PF + 1][NGU];
+    auto read_b = [&](int ks) {
 #pragma unroll
-    for (int ks = 0; ks < RS_KS; ++ks) {
-      if (ks < nks) {
-        vec_t a = a_in[ks];
-        if (32 * ks + kl >= Npad) {
+      for (int u = 0; u < NGU; ++u)
+        bq[ks % (PF + 1)][u] = *reinterpret_cast<const vec_t*>(bcol + 8 * (4 * RS_BN * ks + 16 * u));
+    };
 #pragma unroll
-          for (int e = 0; e < 8; ++e) a[e] = L(0.0f);
-        }
+    for (int ks = 0; ks < PF && ks < NKS; ++ks) read_b(ks);
 #pragma unroll
-        for (int u = 0; u < NGU; ++u) {
-          const vec_t b = *reinterpret_cast<const vec_t*>(bcol + 8 * (4 * RS_BN * ks + 16 * u));
-          acc[u][ks % NJ] = Mfma32<L>::run(a, b, acc[u][ks % NJ]);
-        }
-      }
+    for (int ks = 0; ks < NKS; ++ks) {
+      if (ks + PF < NKS) read_b(ks + PF);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < NGU; ++u)
+        acc[u][ks % NJ] = Mfma32<L>::run(a[ks], bq[ks % (PF + 1)][u], acc[u][ks % NJ]);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    const float hm = (float)g.hm, beta = (float)g.beta;
+    const int m_ep = rb * 16 + 4 * (lane >> 4);
 #pragma unroll
     for (int u = 0; u < NGU; ++u) {
 #pragma unroll
       for (int j = 1; j < NJ; ++j) acc[u][0] += acc[u][j];
       const int nl = (g0 + u) * 16 + (lane & 15);
       const int n = n0 + nl;
-      if (n >= ncols) continue;
+      if (n >= ncols || sc[nl] == 0.0f) continue;
       const float unscale = beta / sc[nl];
-      float4* c = reinterpret_cast<float4*>(C + (size_t)n * Npad + m_ep);
       float4 v;
-      v.x = hm * (bv[u].x + unscale * acc[u][0][0]);
-      v.y = hm * (bv[u].y + unscale * acc[u][0][1]);
-      v.z = hm * (bv[u].z + unscale * acc[u][0][2]);
-      v.w = hm * (bv[u].w + unscale * acc[u][0][3]);
-      if (g.mode == EPI_SPLIT_ADD) {
-        float4 o = *c;
-        o.x += v.x;
-        o.y += v.y;
-        o.z += v.z;
-        o.w += v.w;
-        *c = o;
-      } else {
-        *c = v;
+      v.x = hm * (e.b[u].x + unscale * acc[u][0][0]);
+      v.y = hm * (e.b[u].y + unscale * acc[u][0][1]);
+      v.z = hm * (e.b[u].z + unscale * acc[u][0][2]);
+      v.w = hm * (e.b[u].w + unscale * acc[u][0][3]);
+      if (add) {
+        v.x += e.c[u].x;
+        v.y += e.c[u].y;
+        v.z += e.c[u].z;
+        v.w += e.c[u].w;
       }
+      *reinterpret_cast<float4*>(C + (size_t)n * Npad + m_ep) = v;
     }
   }
 };
 
-template <typename L>
+template <typename L, int NKS>
 __global__ void __launch_bounds__(256) gemm_rs_lp_kernel(GemmArgs g) {
+  typedef RsLpRows<L, NKS, RS_NG> Rows;
+  typedef RsLpRows<L, NKS, 1> Rows1;
   typedef typename Mfma32<L>::vec_t vec_t;
   extern __shared__ float rs_lds_lp[];
   const L* __restrict__ A = static_cast<const L*>(g.A);
   const float* __restrict__ B = static_cast<const float*>(g.B);
   float* __restrict__ C = static_cast<float*>(g.C);
-  const int Npad = g.Npad, ncols = g.ncols, K32 = rs_k32(Npad);
+  const int Npad = g.Npad, ncols = g.ncols;
   const int n0 = blockIdx.x * RS_BN;
   const int tid = threadIdx.x;
   float* sc = rs_lds_lp;                               // [RS_BN] column scales
   L* Bs = reinterpret_cast<L*>(rs_lds_lp + RS_BN);     // records (q, n), 8 values each
+  bool live = false;
   for (int j = tid; j < RS_BN; j += 256) {
-    float s = 1.0f;
-    const int n = n0 + j;
-    if (g.colscale && n < ncols) {
-      const float mx = g.colscale[n];
-      if (mx > 0.0f && isfinite(mx)) s = exp2f(-ceilf(log2f(mx)));
-    }
+    const float s = lp_col_scale(g, n0 + j);
     sc[j] = s;
+    live = live || (s != 0.0f && n0 + j < ncols);
   }
-  __syncthreads();
+  if (!__syncthreads_or(live)) return;  // no column of the workgroup needs work
   // staging, column index fastest; 8 vector pairs per thread in flight at a
   // time (clamped addresses, values outside the matrix replaced by zeros)
-  const int total = RS_BN * (K32 / 8);
+  const int total = RS_BN * (4 * NKS);
   for (int i0 = tid; i0 < total; i0 += 256 * 8) {
     float4 lo[8], hi[8];
 #pragma unroll
@@ -680,30 +721,58 @@ __global__ void __launch_bounds__(256) gemm_rs_lp_kernel(GemmArgs g) {
   __syncthreads();
   const int wave = tid >> 6, lane = tid & 63;
   const int nrb = Npad / 16, full = nrb & ~3;
-  // full row blocks: the next row block's operator rows are in flight while
-  // the current one is multiplied (two register images)
+  const float hm = (float)g.hm, beta = (float)g.beta;
+  const bool add = g.mode == EPI_SPLIT_ADD;
+  // full row blocks, four per round (one per wave); the starting row block
+  // rotates with the workgroup as in the FP32 kernel
   {
-    vec_t cur[RS_KS], nxt[RS_KS];
-    if (wave < full) RsLpRows<L, RS_NG>::load(A, Npad, wave, lane, cur);
-    for (int rb = wave; rb < full; rb += 4) {
-      if (rb + 4 < full) RsLpRows<L, RS_NG>::load(A, Npad, rb + 4, lane, nxt);
+    const int rot = full > 0 ? (blockIdx.x / 8) % full : 0;
+    auto phys = [&](int i) { return i + rot < full ? i + rot : i + rot - full; };
+    vec_t a0[NKS], a1[NKS];
+    typename Rows::Epi e;
+    if (wave < full) Rows::load(A, Npad, phys(wave), lane, a0);
+    for (int i = wave; i < full; i += 8) {
+      Rows::load_epi(B, C, Npad, phys(i), 0, n0, ncols, add, lane, e);
+      if (i + 4 < full) Rows::load(A, Npad, phys(i + 4), lane, a1);
       __builtin_amdgcn_sched_barrier(0);
-      RsLpRows<L, RS_NG>::run(cur, Bs, Npad, rb, 0, B, C, sc, n0, ncols, g, lane);
-#pragma unroll
-      for (int ks = 0; ks < RS_KS; ++ks) cur[ks] = nxt[ks];
+      Rows::run(a0, Bs, Npad, phys(i), 0, C, sc, n0, ncols, hm, beta, add, lane, e);
+      if (i + 4 >= full) break;
+      Rows::load_epi(B, C, Npad, phys(i + 4), 0, n0, ncols, add, lane, e);
+      if (i + 8 < full) Rows::load(A, Npad, phys(i + 8), lane, a0);
+      __builtin_amdgcn_sched_barrier(0);
+      Rows::run(a1, Bs, Npad, phys(i + 4), 0, C, sc, n0, ncols, hm, beta, add, lane, e);
     }
   }
+  // the remaining row blocks one column group at a time
   for (int u = wave; u < (nrb - full) * RS_NG; u += 4) {
-    vec_t a[RS_KS];
-    RsLpRows<L, 1>::load(A, Npad, full + u / RS_NG, lane, a);
-    RsLpRows<L, 1>::run(a, Bs, Npad, full + u / RS_NG, u % RS_NG, B, C, sc, n0, ncols, g, lane);
+    const int rb = full + u / RS_NG, g0 = u % RS_NG;
+    vec_t a[NKS];
+    typename Rows1::Epi e;
+    Rows1::load_epi(B, C, Npad, rb, g0, n0, ncols, add, lane, e);
+    Rows1::load(A, Npad, rb, lane, a);
+    Rows1::run(a, Bs, Npad, rb, g0, C, sc, n0, ncols, hm, beta, add, lane, e);
   }
 }
 
-static const void* rs_kernel(int kind) {
+template <typename L>
+static const void* rs_lp_kernel(int nks) {
+  switch (nks) {
+    case 3: return (const void*)gemm_rs_lp_kernel<L, 3>;
+    case 6: return (const void*)gemm_rs_lp_kernel<L, 6>;
+    case 9: return (const void*)gemm_rs_lp_kernel<L, 9>;
+    case 12: return (const void*)gemm_rs_lp_kernel<L, 12>;
+    case 15: return (const void*)gemm_rs_lp_kernel<L, 15>;
+    case 18: return (const void*)gemm_rs_lp_kernel<L, 18>;
+    case 21: return (const void*)gemm_rs_lp_kernel<L, 21>;
+    case 24: return (const void*)gemm_rs_lp_kernel<L, 24>;
+    default: return nullptr;
+  }
+}
+
+static const void* rs_kernel(int kind, int npad) {
   return kind == 0 ? (const void*)gemm_rs_f32_kernel
-       : kind == 2 ? (const void*)gemm_rs_lp_kernel<__bf16>
-       : kind == 3 ? (const void*)gemm_rs_lp_kernel<_Float16>
+       : kind == 2 ? rs_lp_kernel<__bf16>(rs_nks(npad))
+       : kind == 3 ? rs_lp_kernel<_Float16>(rs_nks(npad))
                    : nullptr;
 }
 
@@ -712,15 +781,15 @@ static const void* rs_kernel(int kind) {
 hipError_t gemm_prepare(int kind, int tile, int npad) {
   if (tile != kNumTilesTiled) return hipSuccess;
   const size_t smem = rs_lds_bytes(kind, npad);
-  if (!rs_kernel(kind) || smem == 0 || smem > 160 * 1024) return hipErrorInvalidValue;
+  const void* fn = rs_kernel(kind, npad);
+  if (!fn || smem == 0 || smem > 160 * 1024) return hipErrorInvalidValue;
   if (smem <= 64 * 1024) return hipSuccess;
-  return hipFuncSetAttribute(rs_kernel(kind), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)smem);
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
 }
 
 static hipError_t run_gemm_rs(int kind, const GemmArgs& g, hipStream_t st) {
   const size_t smem = rs_lds_bytes(kind, g.Npad);
-  const void* fn = rs_kernel(kind);
+  const void* fn = rs_kernel(kind, g.Npad);
   if (!fn || smem == 0 || smem > 160 * 1024) return hipErrorInvalidValue;
   GemmArgs a = g;
   void* args[] = {&a};

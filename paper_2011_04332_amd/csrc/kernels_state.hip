@@ -69,93 +69,154 @@ __global__ void __launch_bounds__(256) update_kernel(ClassSlice<T> cs, T* __rest
 
 // Refinement residual res = r - A_c delta for each cell, with the per-cell
 // system A_c = (m/h^2 + w_v) I + (w_s + w_a) L_tri + w_b L_bend (fixed-width
-// rows of the two Laplacians, shared by the class). One workgroup per cell
-// with one thread per row (up to 1024 rows at a time), so that a wave has few
-// memory round trips in sequence and many waves share each SIMD. The cell's
-// delta is staged in LDS (N + 1 values per coordinate, the last one 0 for
-// padding entries); products accumulate in FP64. colmax: per column max
-// |res| (FP16 scaling): wave maxima, then LDS atomic max on the bit patterns
-// of the non-negative floats.
-template <typename T>
-__global__ void __launch_bounds__(1024) residual_kernel(ClassSlice<T> cs, const T* __restrict__ rhs,
-                                                        const T* __restrict__ delta,
-                                                        T* __restrict__ res,
-                                                        const T* __restrict__ weights,
-                                                        float* __restrict__ colmax, double h) {
+// rows of the two Laplacians, shared by the class). One workgroup handles CPB
+// cells with one thread per row (up to 768 rows at a time): the row's table
+// entries are fetched once and applied to all CPB cells, so the class tables
+// are read from L2 once per CPB cells, and a thread has three round trips to
+// memory in sequence (the cells' delta into LDS; the right-hand sides with
+// the first table entries; the remaining entries). delta is staged as
+// [cell][coordinate][N + 1] (the last value 0, for padding entries);
+// products accumulate in FP64. colmax: per column max |res| (FP16 scaling):
+// wave maxima, then LDS atomic max on the bit patterns of the non-negative
+// floats.
+//
+// need (optional, with colmax): max |r| of each column of the right-hand side
+// that the sweeps correct. A cell whose need_factor * max |r| (a bound on the
+// error the previous solve left in its delta) is at most need_thr needs no
+// further correction: its colmax entries are set to 0, which tells the
+// correcting product to leave its columns alone. A workgroup whose cells all
+// need none returns without reading anything else.
+constexpr int kResidualBlock = 768;
+
+template <typename T, int CPB>
+__global__ void __launch_bounds__(kResidualBlock) residual_kernel(
+    ClassSlice<T> cs, const T* __restrict__ rhs, const T* __restrict__ delta, T* __restrict__ res,
+    const T* __restrict__ weights, float* __restrict__ colmax, const float* __restrict__ need,
+    double need_factor, double need_thr, double h) {
   extern __shared__ double smem_res[];
-  unsigned* cmx = reinterpret_cast<unsigned*>(smem_res);  // [3]
-  T* sd = reinterpret_cast<T*>(smem_res + 2);             // [3][N + 1]
-  const int N = cs.cv.N, Npad = cs.cv.Npad, DL = cs.cv.DL;
-  const int lc = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-  const long long cb = cs.elem0 + 3LL * lc * Npad;
+  unsigned* cmx = reinterpret_cast<unsigned*>(smem_res);  // [3 CPB]
+  T* sd = reinterpret_cast<T*>(smem_res + (3 * CPB + 1) / 2);  // [CPB][3][N + 1]
+  const int N = cs.cv.N, Npad = cs.cv.Npad, DL = cs.cv.DL, N1 = N + 1;
+  const int c0 = blockIdx.x * CPB, tid = threadIdx.x, nt = blockDim.x;
+  const int ncell = min(CPB, cs.n_cells - c0);
+  bool live[CPB];
+  bool any_live = false;
+#pragma unroll
+  for (int c = 0; c < CPB; ++c) {
+    live[c] = c < ncell;
+    if (need && colmax && c < ncell) {
+      const float* nc = need + cs.col0 + 3LL * (c0 + c);
+      const double mx = fmax(fmax((double)nc[0], (double)nc[1]), (double)nc[2]);
+      live[c] = !(need_factor * mx <= need_thr);  // NaN: live
+    }
+    any_live = any_live || live[c];
+  }
+  if (!any_live) {
+    if (colmax && tid < 3 * ncell) colmax[cs.col0 + 3LL * c0 + tid] = 0.0f;
+    return;
+  }
+  const T* __restrict__ dcell = delta + cs.elem0 + 3LL * c0 * Npad;
+  const T* __restrict__ rcell = rhs + cs.elem0 + 3LL * c0 * Npad;
+  T* __restrict__ ocell = res + cs.elem0 + 3LL * c0 * Npad;
   const int* __restrict__ lcol = cs.cv.lap_col;
   const T* __restrict__ lt = cs.cv.lap_t;
   const T* __restrict__ lb = cs.cv.lap_b;
-  for (int v = tid; v <= N; v += nt) {
-    const int vc = min(v, N - 1);
-    const T dx = delta[cb + vc], dy = delta[cb + Npad + vc], dz = delta[cb + 2 * Npad + vc];
-    sd[v] = v < N ? dx : T(0);
-    sd[(N + 1) + v] = v < N ? dy : T(0);
-    sd[2 * (N + 1) + v] = v < N ? dz : T(0);
+  for (int v0 = 0; v0 <= N; v0 += nt) {
+    const int v = v0 + tid;
+    if (v <= N) {
+      const int vc = min(v, N - 1);
+      T dv[CPB][3];
+#pragma unroll
+      for (int c = 0; c < CPB; ++c)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          dv[c][d] = dcell[(size_t)(3 * min(c, ncell - 1) + d) * Npad + vc];
+#pragma unroll
+      for (int c = 0; c < CPB; ++c)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sd[(3 * c + d) * N1 + v] = (v < N && c < ncell) ? dv[c][d] : T(0);
+    }
   }
-  if (tid < 3) cmx[tid] = 0u;
+  if (tid < 3 * CPB) cmx[tid] = 0u;
   __syncthreads();
-  const int cell = cs.cell0 + lc;
-  double w[4];
+  double diag[CPB], wt[CPB], wb[CPB];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) w[k] = weights ? (double)weights[4 * cell + k] : (double)cs.w_nom[k];
-  const double diag = (double)cs.mass / (h * h) + w[3];
-  const double wt = w[0] + w[1], wb = w[2];
-  float cm[3] = {0.f, 0.f, 0.f};
+  for (int c = 0; c < CPB; ++c) {
+    const int cell = cs.cell0 + c0 + min(c, ncell - 1);
+    double w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = weights ? (double)weights[4 * cell + k] : (double)cs.w_nom[k];
+    diag[c] = (double)cs.mass / (h * h) + w[3];
+    wt[c] = w[0] + w[1];
+    wb[c] = w[2];
+  }
+  float cm[CPB][3];
+#pragma unroll
+  for (int c = 0; c < CPB; ++c) cm[c][0] = cm[c][1] = cm[c][2] = 0.f;
   for (int v = tid; v < Npad; v += nt) {
-    double a0 = 0, a1 = 0, a2 = 0;
-    if (v < N) {
-      const T r0 = rhs[cb + v], r1 = rhs[cb + Npad + v], r2 = rhs[cb + 2 * Npad + v];
-      a0 = diag * (double)sd[v];
-      a1 = diag * (double)sd[(N + 1) + v];
-      a2 = diag * (double)sd[2 * (N + 1) + v];
-      // row entries fetched 8 at a time (the slots past the last clamped,
-      // their weight zeroed)
-      for (int k0 = 0; k0 < DL; k0 += 8) {
-        int jj[8];
-        T ct[8], cbv[8];
+    double a[CPB][3];
+    T r[CPB][3];
+    const int vr = min(v, N - 1);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int e = min(k0 + u, DL - 1) * N + v;
-          jj[u] = lcol[e];
-          ct[u] = lt[e];
-          cbv[u] = lb[e];
-        }
-        __builtin_amdgcn_sched_barrier(0);
+    for (int c = 0; c < CPB; ++c)
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const double c = k0 + u < DL ? wt * (double)ct[u] + wb * (double)cbv[u] : 0.0;
-          const int j = jj[u];
-          a0 += c * (double)sd[j];
-          a1 += c * (double)sd[(N + 1) + j];
-          a2 += c * (double)sd[2 * (N + 1) + j];
+      for (int d = 0; d < 3; ++d) {
+        r[c][d] = rcell[(size_t)(3 * min(c, ncell - 1) + d) * Npad + vr];
+        a[c][d] = diag[c] * (double)sd[(3 * c + d) * N1 + vr];
+      }
+    // row entries fetched 8 at a time (the slots past the last clamped,
+    // their weight zeroed)
+    for (int k0 = 0; k0 < DL; k0 += 8) {
+      int jj[8];
+      T ct[8], cbv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = min(k0 + u, DL - 1) * N + vr;
+        jj[u] = lcol[e];
+        ct[u] = lt[e];
+        cbv[u] = lb[e];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool on = k0 + u < DL;
+        const int j = jj[u];
+#pragma unroll
+        for (int c = 0; c < CPB; ++c) {
+          const double cf = on ? wt[c] * (double)ct[u] + wb[c] * (double)cbv[u] : 0.0;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) a[c][d] += cf * (double)sd[(3 * c + d) * N1 + j];
         }
       }
-      a0 = (double)r0 - a0;
-      a1 = (double)r1 - a1;
-      a2 = (double)r2 - a2;
     }
-    res[cb + v] = T(a0);
-    res[cb + Npad + v] = T(a1);
-    res[cb + 2 * Npad + v] = T(a2);
-    cm[0] = fmaxf(cm[0], fabsf((float)a0));
-    cm[1] = fmaxf(cm[1], fabsf((float)a1));
-    cm[2] = fmaxf(cm[2], fabsf((float)a2));
+#pragma unroll
+    for (int c = 0; c < CPB; ++c) {
+      if (c < ncell) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const double o = v < N ? (double)r[c][d] - a[c][d] : 0.0;
+          ocell[(size_t)(3 * c + d) * Npad + v] = T(o);
+          cm[c][d] = fmaxf(cm[c][d], fabsf((float)o));
+        }
+      }
+    }
   }
   if (colmax) {
-    // wave maxima first, then one LDS atomic per wave and coordinate
+    // wave maxima first, then one LDS atomic per wave and column
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const float mx = wave_max(cm[d]);
-      if ((tid & (kWave - 1)) == 0) atomicMax(&cmx[d], __float_as_uint(mx));
-    }
+    for (int c = 0; c < CPB; ++c)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const float mx = wave_max(cm[c][d]);
+        if ((tid & (kWave - 1)) == 0) atomicMax(&cmx[3 * c + d], __float_as_uint(mx));
+      }
     __syncthreads();
-    if (tid < 3) colmax[cs.col0 + 3LL * lc + tid] = __uint_as_float(cmx[tid]);
+    if (tid < 3 * ncell) {
+      bool lv = false;
+#pragma unroll
+      for (int c = 0; c < CPB; ++c) lv = lv || (tid / 3 == c && live[c]);
+      colmax[cs.col0 + 3LL * c0 + tid] = lv ? __uint_as_float(cmx[tid]) : 0.0f;
+    }
   }
 }
 
@@ -203,17 +264,33 @@ hipError_t launch_update(const ClassSlice<T>& cs, T* pos, T* vel, long long sumN
   return hipGetLastError();
 }
 
+template <typename T, int CPB>
+static size_t residual_smem(int N) {
+  return sizeof(double) * ((3 * CPB + 1) / 2) + sizeof(T) * 3 * CPB * ((size_t)N + 1);
+}
+
+// Cells per workgroup: the most (up to 6 in FP32, 4 in FP64) whose delta fits
+// 64 KB of LDS.
 template <typename T>
 hipError_t launch_residual(const ClassSlice<T>& cs, const T* rhs, const T* delta, T* res,
-                           const T* weights, float* colmax, double h, hipStream_t st) {
+                           const T* weights, float* colmax, const float* need, double need_factor,
+                           double need_thr, double h, hipStream_t st) {
   if (cs.n_cells == 0) return hipSuccess;
   const int N = cs.cv.N;
-  const size_t smem = 2 * sizeof(double) + sizeof(T) * 3 * ((size_t)N + 1);
-  if (smem > 64 * 1024) return hipErrorInvalidValue;
-  const int block = std::min(1024, (cs.cv.Npad + 63) / 64 * 64);
-  hipLaunchKernelGGL(residual_kernel<T>, dim3(cs.n_cells), dim3(block), smem, st, cs, rhs, delta,
-                     res, weights, colmax, h);
-  return hipGetLastError();
+  const int block = std::min(kResidualBlock, (cs.cv.Npad + 63) / 64 * 64);
+  const size_t cap = 64 * 1024;
+  auto go = [&](auto kern, int cpb, size_t smem) {
+    hipLaunchKernelGGL(kern, dim3((cs.n_cells + cpb - 1) / cpb), dim3(block), smem, st, cs, rhs,
+                       delta, res, weights, colmax, need, need_factor, need_thr, h);
+    return hipGetLastError();
+  };
+  if constexpr (sizeof(T) == 4) {  // (6 FP64 cells would not fit the registers)
+    if (residual_smem<T, 6>(N) <= cap) return go(residual_kernel<T, 6>, 6, residual_smem<T, 6>(N));
+  }
+  if (residual_smem<T, 4>(N) <= cap) return go(residual_kernel<T, 4>, 4, residual_smem<T, 4>(N));
+  if (residual_smem<T, 2>(N) <= cap) return go(residual_kernel<T, 2>, 2, residual_smem<T, 2>(N));
+  if (residual_smem<T, 1>(N) <= cap) return go(residual_kernel<T, 1>, 1, residual_smem<T, 1>(N));
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -230,7 +307,8 @@ hipError_t launch_volume(const ClassSlice<T>& cs, const T* pos, long long sumN, 
   template hipError_t launch_update<T>(const ClassSlice<T>&, T*, T*, long long, const T*, double, \
                                        hipStream_t);                                             \
   template hipError_t launch_residual<T>(const ClassSlice<T>&, const T*, const T*, T*, const T*, \
-                                         float*, double, hipStream_t);                           \
+                                         float*, const float*, double, double, double,           \
+                                         hipStream_t);                                           \
   template hipError_t launch_volume<T>(const ClassSlice<T>&, const T*, long long, double*,       \
                                        hipStream_t);
 NPFEM_INST(float)

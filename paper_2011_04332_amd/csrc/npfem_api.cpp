@@ -79,6 +79,7 @@ struct ClassState {
   void* op = nullptr;          // stored global-step operator [Npad][Npad]
   double beta = 0.0;           // split scale (low precision)
   double kappa = 0.0;          // max row sum of |Ainv - (h^2/m) I| / (h^2/m) (low precision)
+  double r_rest = 0.0;         // max distance of a rest vertex from the rest centroid
   int local_block = 256;
   int gemm_tile = 3;
   int DT = 0, DH = 0, DL = 0;  // padded incidence and Laplacian widths
@@ -110,7 +111,8 @@ struct npfem_batch_s {
   void* cterm = nullptr;
   void* rhs = nullptr;
   void* res = nullptr;
-  float* colmax = nullptr;
+  float* colmax = nullptr;      // max |r| per column (16-bit products)
+  float* colmax_res = nullptr;  // max |res| per column of the correction sweeps
   int* status = nullptr;
   double* energy = nullptr;
   int energy_cap = 0;    // iterations the energy buffer holds
@@ -122,6 +124,7 @@ struct npfem_batch_s {
   std::vector<int> cell_class;       // [n_cells] mesh class of each cell
   double dt = -1.0;
   int n_refine = 0;
+  double rho = 0.0, rho_w = 0.0;  // contraction estimates of the sweeps (choose_refine)
   bool tuned = false;
   hipGraphExec_t graph = nullptr;
   const void* graph_forces = nullptr;
@@ -277,6 +280,17 @@ int upload_class(ClassState& c) {
   // fixed-width, vertex-major incidence ([N][slot]); entries keep ascending
   // element order, padding contributes zero
   const int N = M.N;
+  {
+    double cen[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
+    for (int i = 0; i < N; ++i)
+      for (int d = 0; d < 3; ++d) cen[d] += M.X[3 * (size_t)i + d] / N;
+    for (int i = 0; i < N; ++i) {
+      double q = 0.0;
+      for (int d = 0; d < 3; ++d) q += (M.X[3 * (size_t)i + d] - cen[d]) * (M.X[3 * (size_t)i + d] - cen[d]);
+      r2 = std::max(r2, q);
+    }
+    c.r_rest = std::sqrt(r2);
+  }
   c.DT = 0;
   c.DH = 0;
   for (int i = 0; i < N; ++i) {
@@ -428,6 +442,8 @@ int choose_refine(npfem_batch_s* b, double dt, int* out) {
     }
   }
   const double rho = rho_w + rho_lp + rho_w * rho_lp;
+  b->rho = rho;
+  b->rho_w = rho_w;
   if (rho >= 0.9)
     return fail(NPFEM_ERR_INVALID_ARG,
                 "the shared operator does not contract the correction (estimate %.3g: per-cell "
@@ -580,7 +596,7 @@ int enqueue_solve(npfem_batch_s* b, ClassState& c, T* B, T* C, double h, hipStre
   T* res = static_cast<T*>(b->res);
   const T* w = b->per_cell ? static_cast<const T*>(b->weights_dev) : nullptr;
   const bool lp = b->gemm_kind >= 2;
-  float* colmax = (b->gemm_kind == 3) ? b->colmax : nullptr;
+  float* colmax = lp ? b->colmax : nullptr;
   GemmArgs g;
   g.A = c.op;
   g.B = B + c.elem0;
@@ -592,11 +608,23 @@ int enqueue_solve(npfem_batch_s* b, ClassState& c, T* B, T* C, double h, hipStre
   g.hm = h * h / c.mat.vertex_mass;
   g.beta = c.beta;
   NPFEM_TIMED(NPFEM_KERNEL_GLOBAL, launch_gemm(b->gemm_kind, c.gemm_tile, g, st), "global step");
+  // 16-bit products with the automatic sweep count: sweep s + 1 runs for a
+  // cell only while the bound rho^(s+1) |delta| on the error left in its delta
+  // exceeds the FP32 rounding of the cell's coordinates (2^-24 of its rest
+  // radius), with |delta| <= |A_c^-1| max |r| <= hm (1 + kappa) / (1 - rho_w)
+  // max |r|; the per-cell test runs on the device (residual step).
+  const bool adapt = lp && b->n_refine_opt < 0 && !b->fp64;
+  double bound = g.hm * (1.0 + c.kappa) / std::max(1e-300, 1.0 - b->rho_w);
   for (int s = 0; s < b->n_refine; ++s) {
+    bound *= b->rho;
     NPFEM_TIMED(NPFEM_KERNEL_RESIDUAL,
-                launch_residual<T>(slice_of<T>(c), B, C, res, w, colmax, h, st), "residual");
+                launch_residual<T>(slice_of<T>(c), B, C, res, w, lp ? b->colmax_res : nullptr,
+                                   adapt ? colmax : nullptr, bound,
+                                   std::ldexp(1.0, -24) * c.r_rest, h, st),
+                "residual");
     GemmArgs r = g;
     r.B = res + c.elem0;
+    r.colscale = lp ? b->colmax_res + c.col0 : nullptr;
     r.mode = lp ? EPI_SPLIT_ADD : EPI_ADD;
     NPFEM_TIMED(NPFEM_KERNEL_GLOBAL, launch_gemm(b->gemm_kind, c.gemm_tile, r, st), "refinement");
   }
@@ -616,7 +644,7 @@ int enqueue_class_step(npfem_batch_s* b, ClassState& c, T* pos, T* vel, const T*
   T* cterm = static_cast<T*>(b->cterm);
   T* rhs = static_cast<T*>(b->rhs);
   const T* w = b->per_cell ? static_cast<const T*>(b->weights_dev) : nullptr;
-  float* colmax = (b->gemm_kind == 3) ? b->colmax : nullptr;
+  float* colmax = (b->gemm_kind >= 2) ? b->colmax : nullptr;
   const bool want_energy = (b->flags & NPFEM_OPT_ENERGY) != 0 && !dslots;
   auto slot = [&](int k) { return dslots ? dslots[k] : delta; };
   NPFEM_TIMED(NPFEM_KERNEL_PREDICT,
@@ -1082,6 +1110,8 @@ int npfem_create_batch(const npfem_mesh* meshes, int32_t n_meshes, const int32_t
   void* p;
   if ((rc = dalloc(b.get(), &p, sizeof(float) * (size_t)b->total_cols, "colmax"))) return rc;
   b->colmax = static_cast<float*>(p);
+  if ((rc = dalloc(b.get(), &p, sizeof(float) * (size_t)b->total_cols, "colmax_res"))) return rc;
+  b->colmax_res = static_cast<float*>(p);
   if ((rc = dalloc(b.get(), &p, 64, "status"))) return rc;
   b->status = static_cast<int*>(p);
   if ((rc = dalloc(b.get(), &p, sizeof(double) * (size_t)n_cells, "volume"))) return rc;

@@ -129,7 +129,8 @@ template <typename T>
 hipError_t local_prepare(const ClassView<T>& cv, int block);
 template <typename T>
 hipError_t launch_residual(const ClassSlice<T>& cs, const T* rhs, const T* delta, T* res,
-                           const T* weights, float* colmax, double h, hipStream_t st);
+                           const T* weights, float* colmax, const float* need, double need_factor,
+                           double need_thr, double h, hipStream_t st);
 template <typename T>
 hipError_t launch_volume(const ClassSlice<T>& cs, const T* pos, long long sumN, double* out,
                          hipStream_t st);
