@@ -252,7 +252,9 @@ def main():
                           cell_weights=None if s.uniform_weights() else s.weights,
                           precision=a.precision, kernel_timing=True)
         for k, cfg in enumerate(configs):
-            bt.set_config(k, cfg)
+            # pins the launch shapes; the sweep count stays automatic (with
+            # 16-bit products, sweeps a cell does not need are skipped)
+            bt.set_config(k, (cfg[0], cfg[1], cfg[2], -1))
         for i in range(a.steps):
             bt.step(f, dt, n_iter)
             if i + 1 == cpu_steps:
