@@ -111,10 +111,12 @@ def gemm_flops(s):
 
 # Algorithmic FLOPs of the local step per element (FMA = 2, add/mul/sqrt/rcp = 1),
 # counted from the operations it performs: strain + area projection and
-# contribution per triangle, bending per hinge, one volume pass per vertex
+# contribution per triangle, bending per hinge (both against q only: the
+# kernel forms the increment right-hand side), one volume pass per vertex
 # (36 per triangle for the corner cross products, 33 per vertex), the two
-# gathers (12 per triangle corner, 24 per hinge) and the final sum.
-TRI_FLOPS, HINGE_FLOPS = 251, 60
+# gathers (12 per triangle corner, 24 per hinge) and the per-vertex inertia
+# term and final sum (9 per vertex).
+TRI_FLOPS, HINGE_FLOPS = 221, 35
 VOL_TRI_FLOPS, VOL_VERT_FLOPS = 36, 33
 VOLUME_PASSES = 1  # the minimum: the settling test can stop after the first pass
 
@@ -124,7 +126,7 @@ def local_flops(s):
     for n_c, N, F, E in class_counts(s):
         per_cell = (TRI_FLOPS * F + HINGE_FLOPS * E
                     + VOLUME_PASSES * (VOL_TRI_FLOPS * F + VOL_VERT_FLOPS * N) + 6 * N
-                    + 12 * 3 * F + 24 * E + 3 * N)
+                    + 12 * 3 * F + 24 * E + 9 * N)
         total += n_c * per_cell
     return total
 

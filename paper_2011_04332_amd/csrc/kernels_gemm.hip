@@ -170,7 +170,9 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 1)) gemm_kernel(Gem
     }
   }
 
-  // epilogue: each 16x16 block lies inside [0, Npad) or wholly outside it
+  // epilogue: each 16x16 block lies inside [0, Npad) or wholly outside it;
+  // C = D + product (D = C when accumulating, none if null)
+  const T* Dadd = g.mode == EPI_ADD ? C : static_cast<const T*>(g.D);
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     const int mb = m0 + wm * WM + i * 16;
@@ -180,9 +182,11 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 1)) gemm_kernel(Gem
       const int n = n0 + wn * WN + j * 16 + (lane & 15);
       if (n >= ncols) continue;
       T* c = C + (size_t)n * Npad + mb;
-      if (g.mode == EPI_ADD) {
+      if (Dadd) {
+        const T* d = Dadd + (size_t)n * Npad + mb;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) c[Mfma4<T>::row(lane, r)] += acc[i][j][r];
+        for (int r = 0; r < 4; ++r)
+          c[Mfma4<T>::row(lane, r)] = d[Mfma4<T>::row(lane, r)] + acc[i][j][r];
       } else {
 #pragma unroll
         for (int r = 0; r < 4; ++r) c[Mfma4<T>::row(lane, r)] = acc[i][j][r];
@@ -340,6 +344,7 @@ __global__ void __launch_bounds__(256) gemm_lp_kernel(GemmArgs g) {
   }
 
   const float hm = (float)g.hm, beta = (float)g.beta;
+  const float* Dadd = g.mode == EPI_SPLIT_ADD ? C : static_cast<const float*>(g.D);
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     const int m = m0 + wm * WM + i * 16 + (lane >> 4) * 4;
@@ -352,9 +357,10 @@ __global__ void __launch_bounds__(256) gemm_lp_kernel(GemmArgs g) {
       const float unscale = beta / sc_in[nn];
       const float* bcol = B + (size_t)n * Npad + m;
       float* c = C + (size_t)n * Npad + m;
-      if (g.mode == EPI_SPLIT_ADD) {
+      if (Dadd) {
+        const float* d = Dadd + (size_t)n * Npad + m;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) c[r] += hm * (bcol[r] + unscale * acc[i][j][r]);
+        for (int r = 0; r < 4; ++r) c[r] = d[r] + hm * (bcol[r] + unscale * acc[i][j][r]);
       } else {
 #pragma unroll
         for (int r = 0; r < 4; ++r) c[r] = hm * (bcol[r] + unscale * acc[i][j][r]);
@@ -393,7 +399,7 @@ __host__ __device__ inline int rs_k32(int npad) { return (npad + 31) / 32 * 32; 
 template <int NR, int NGU>
 __device__ __forceinline__ void rs_rows_f32(const float* __restrict__ A, const float* Bs, int Npad,
                                             int rb, int g0, float* __restrict__ C, int n0,
-                                            int ncols, int mode, int lane) {
+                                            int ncols, const float* Dadd, int lane) {
   constexpr int NJ = (NR * NGU == 1) ? 4 : 1;
   constexpr int D = 4;  // prefetch distance in 16-k groups
   floatx4 acc[NR][NGU][NJ];
@@ -450,6 +456,19 @@ __device__ __forceinline__ void rs_rows_f32(const float* __restrict__ A, const f
   for (int i = 0; i < D; ++i)
 #pragma unroll
     for (int r = 0; r < NR; ++r) cur[i][r] = load_a(r, i);
+  // the addend of the rows this lane stores, requested after the first
+  // operator groups (so that their wait does not include it) and long before
+  // the epilogue (clamped column index: columns past the last are never stored)
+  float4 dv[NR][NGU];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int u = 0; u < NGU; ++u) {
+      const int n = min(n0 + (g0 + u) * 16 + (lane & 15), ncols - 1);
+      dv[r][u] = Dadd ? *reinterpret_cast<const float4*>(Dadd + (size_t)n * Npad + (rb + r) * 16 +
+                                                         4 * (lane >> 4))
+                      : float4{0.f, 0.f, 0.f, 0.f};
+    }
   int kg = 0;
   for (; kg + D <= nkg; kg += D) {
 #pragma unroll
@@ -478,8 +497,8 @@ __device__ __forceinline__ void rs_rows_f32(const float* __restrict__ A, const f
       float4* c =
           reinterpret_cast<float4*>(C + (size_t)n * Npad + (rb + r) * 16 + 4 * (lane >> 4));
       const float4 v{acc[r][u][0][0], acc[r][u][0][1], acc[r][u][0][2], acc[r][u][0][3]};
-      if (mode == EPI_ADD) {
-        float4 o = *c;
+      if (Dadd) {
+        float4 o = dv[r][u];
         o.x += v.x;
         o.y += v.y;
         o.z += v.z;
@@ -533,12 +552,14 @@ __global__ void __launch_bounds__(256) gemm_rs_f32_kernel(GemmArgs g) {
   const int wave = tid >> 6, lane = tid & 63;
   const int nrb = Npad / 16, full = nrb & ~7;
   const int rot = full > 0 ? 2 * ((blockIdx.x / 8) % (full / 2)) : 0;
+  // C = D + product (D = C when accumulating, none if null)
+  const float* Dadd = g.mode == EPI_ADD ? C : static_cast<const float*>(g.D);
   for (int i = 2 * wave; i < full; i += 8) {
     const int rb = i + rot < full ? i + rot : i + rot - full;
-    rs_rows_f32<2, RS_NG>(A, rs_lds, Npad, rb, 0, C, n0, ncols, g.mode, lane);
+    rs_rows_f32<2, RS_NG>(A, rs_lds, Npad, rb, 0, C, n0, ncols, Dadd, lane);
   }
   for (int u = wave; u < (nrb - full) * RS_NG; u += 4)
-    rs_rows_f32<1, 1>(A, rs_lds, Npad, full + u / RS_NG, u % RS_NG, C, n0, ncols, g.mode, lane);
+    rs_rows_f32<1, 1>(A, rs_lds, Npad, full + u / RS_NG, u % RS_NG, C, n0, ncols, Dadd, lane);
 }
 
 // 16-bit version: the split operator Bt (16-bit, [Npad][Npad]) against the
@@ -552,8 +573,8 @@ __global__ void __launch_bounds__(256) gemm_rs_f32_kernel(GemmArgs g) {
 // A wave holds a whole 16-row block of the operator in registers and
 // fetches the next one into a second register image while it multiplies
 // (the two images alternate, nothing is copied). The epilogue applies
-// C = hm (B + beta / s_n Bt B) (or adds it to C) with B re-read in FP32;
-// those loads, and the C loads of the accumulating mode, are issued before
+// C = D + hm (B + beta / s_n Bt B) (D = C when accumulating) with B re-read
+// in FP32; those loads, and the loads of D, are issued before
 // the next row block's operator loads so that the epilogue waits for them
 // alone.
 constexpr int RS_KS_STEP = 3;
@@ -594,7 +615,7 @@ struct RsLpRows {
   // lane l holds rows 16 rb + 4 (l/16) .. + 3 of column group g0 + u, column
   // l%16 (clamped column index: columns past the last are never stored)
   static __device__ __forceinline__ void load_epi(const float* __restrict__ B,
-                                                  const float* __restrict__ C, int Npad, int rb,
+                                                  const float* __restrict__ D, int Npad, int rb,
                                                   int g0, int n0, int ncols, bool add, int lane,
                                                   Epi& e) {
     const int m_ep = rb * 16 + 4 * (lane >> 4);
@@ -602,7 +623,7 @@ struct RsLpRows {
     for (int u = 0; u < NGU; ++u) {
       const int n = min(n0 + (g0 + u) * 16 + (lane & 15), ncols - 1);
       e.b[u] = *reinterpret_cast<const float4*>(B + (size_t)n * Npad + m_ep);
-      e.c[u] = add ? *reinterpret_cast<const float4*>(C + (size_t)n * Npad + m_ep)
+      e.c[u] = add ? *reinterpret_cast<const float4*>(D + (size_t)n * Npad + m_ep)
                    : float4{0.f, 0.f, 0.f, 0.f};
     }
   }
@@ -722,7 +743,9 @@ __global__ void __launch_bounds__(256) gemm_rs_lp_kernel(GemmArgs g) {
   const int wave = tid >> 6, lane = tid & 63;
   const int nrb = Npad / 16, full = nrb & ~3;
   const float hm = (float)g.hm, beta = (float)g.beta;
-  const bool add = g.mode == EPI_SPLIT_ADD;
+  // C = D + product (D = C when accumulating, none if null)
+  const float* Dadd = g.mode == EPI_SPLIT_ADD ? C : static_cast<const float*>(g.D);
+  const bool add = Dadd != nullptr;
   // full row blocks, four per round (one per wave); the starting row block
   // rotates with the workgroup as in the FP32 kernel
   {
@@ -732,12 +755,12 @@ __global__ void __launch_bounds__(256) gemm_rs_lp_kernel(GemmArgs g) {
     typename Rows::Epi e;
     if (wave < full) Rows::load(A, Npad, phys(wave), lane, a0);
     for (int i = wave; i < full; i += 8) {
-      Rows::load_epi(B, C, Npad, phys(i), 0, n0, ncols, add, lane, e);
+      Rows::load_epi(B, Dadd, Npad, phys(i), 0, n0, ncols, add, lane, e);
       if (i + 4 < full) Rows::load(A, Npad, phys(i + 4), lane, a1);
       __builtin_amdgcn_sched_barrier(0);
       Rows::run(a0, Bs, Npad, phys(i), 0, C, sc, n0, ncols, hm, beta, add, lane, e);
       if (i + 4 >= full) break;
-      Rows::load_epi(B, C, Npad, phys(i + 4), 0, n0, ncols, add, lane, e);
+      Rows::load_epi(B, Dadd, Npad, phys(i + 4), 0, n0, ncols, add, lane, e);
       if (i + 8 < full) Rows::load(A, Npad, phys(i + 8), lane, a0);
       __builtin_amdgcn_sched_barrier(0);
       Rows::run(a1, Bs, Npad, phys(i + 4), 0, C, sc, n0, ncols, hm, beta, add, lane, e);
@@ -748,7 +771,7 @@ __global__ void __launch_bounds__(256) gemm_rs_lp_kernel(GemmArgs g) {
     const int rb = full + u / RS_NG, g0 = u % RS_NG;
     vec_t a[NKS];
     typename Rows1::Epi e;
-    Rows1::load_epi(B, C, Npad, rb, g0, n0, ncols, add, lane, e);
+    Rows1::load_epi(B, Dadd, Npad, rb, g0, n0, ncols, add, lane, e);
     Rows1::load(A, Npad, rb, lane, a);
     Rows1::run(a, Bs, Npad, rb, g0, C, sc, n0, ncols, hm, beta, add, lane, e);
   }

@@ -2,14 +2,22 @@
 // workgroup per cell.
 //
 // For the current iterate q = x + delta (delta form: the global step solves
-// A delta = b - A x), the kernel computes per cell
-//   r = (m/h)v + f                                     (inertia, precomputed)
-//     + sum_t A_t G_t (w_s (Ps_t - F_t(x)) + w_a (Pa_t - F_t(x)))^T
-//     + sum_e w_b c_e K_e (x) (Pb_e - y_e(x))
-//     + w_v (Pv - x)
+// A delta = b - A x, with x the positions at the start of the step and
+// A = (m/h^2) I + S, S the constraint stiffness), the kernel computes per cell
+// the increment right-hand side
+//   r = (m/h)v + f - (m/h^2) delta                 (inertia term, precomputed)
+//     + sum_t A_t G_t (w_s (Ps_t - F_t(q)) + w_a (Pa_t - F_t(q)))^T
+//     + sum_e w_b c_e K_e (x) (Pb_e - y_e(q))
+//     + w_v (Pv - q)
 // where Ps/Pa are the strain/area projections of F_t(q), Pb the bending
 // projection of y_e(q) = sum_r K_e[r] q_r and Pv the closest point of q on the
-// rest-volume surface.
+// rest-volume surface. This is b - A x - A delta (the projections' terms
+// against q instead of x differ by S delta), so the global step's solve
+// returns the next iterate as delta + A^-1 r; the same iteration as
+// delta_next = A^-1 (b - A x), but r no longer needs x at all: only q is
+// staged, the element phases read half as much LDS, and r is small (it
+// vanishes at the fixed point), which also shrinks the absolute error of a
+// 16-bit product.
 //
 // LDS holds the cell's vertices as 16/32-byte records (one vector read per
 // vertex), and the per-element contributions, which each vertex then gathers
@@ -71,9 +79,10 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
   T* __restrict__ rcol = a.rhs + cb;
 
   double* red = smem_local;  // 8 * NW doubles
+  // q: N records and a zero record N, which the padding entries of the volume
+  // fan lists point at (their cross product is 0 only for finite records)
   V4<T>* qs = reinterpret_cast<V4<T>*>(smem_local + 8 * NW);
-  V4<T>* xs = qs + N;
-  T* work = reinterpret_cast<T*>(xs + N);
+  T* work = reinterpret_cast<T*>(qs + N + 1);
 
   T ws, wa, wb, wv;
   if (a.weights) {
@@ -91,20 +100,10 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
   double e_acc = 0.0;
   int bad = 0;
 
-  // ---- stage x and q = x + delta ----
-  for (int v = tid; v < N; v += BLOCK) {
-    V4<T> x, q;
-    x.x = px[v];
-    x.y = py[v];
-    x.z = pz[v];
-    x.w = T(0);
-    q.x = x.x + dcol[v];
-    q.y = x.y + dcol[Npad + v];
-    q.z = x.z + dcol[2 * Npad + v];
-    q.w = T(0);
-    xs[v] = x;
-    qs[v] = q;
-  }
+  // ---- stage q = x + delta ----
+  for (int v = tid; v < N; v += BLOCK)
+    qs[v] = V4<T>{px[v] + dcol[v], py[v] + dcol[Npad + v], pz[v] + dcol[2 * Npad + v], T(0)};
+  if (tid == 0) qs[N] = V4<T>{T(0), T(0), T(0), T(0)};
   __syncthreads();
 
   T acc[VPT][3];
@@ -123,12 +122,11 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
       if (v < N) {
-        const V4<T> x = xs[v];
-        acc[j][0] += wv * (p[j][0] - x.x);
-        acc[j][1] += wv * (p[j][1] - x.y);
-        acc[j][2] += wv * (p[j][2] - x.z);
+        const V4<T> q = qs[v];
+        acc[j][0] += wv * (p[j][0] - q.x);
+        acc[j][1] += wv * (p[j][1] - q.y);
+        acc[j][2] += wv * (p[j][2] - q.z);
         if (want_energy) {
-          const V4<T> q = qs[v];
           const double d0 = (double)q.x - p[j][0], d1 = (double)q.y - p[j][1],
                        d2 = (double)q.z - p[j][2];
           e_acc += 0.5 * (double)wv * (d0 * d0 + d1 * d1 + d2 * d2);
@@ -151,16 +149,12 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
       const T g00 = r0.x, g01 = r0.y, g10 = r0.z, g11 = r0.w, g20 = r1.x, g21 = r1.y;
       const T area = r1.z;
       const V4<T> qa = qs[id.x], qb = qs[id.y], qc = qs[id.z];
-      const V4<T> xa = xs[id.x], xb = xs[id.y], xc = xs[id.z];
-      T fq[3][2], fx[3][2];
+      T fq[3][2];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const T q0 = comp(qa, d), q1 = comp(qb, d), q2 = comp(qc, d);
-        const T x0 = comp(xa, d), x1 = comp(xb, d), x2 = comp(xc, d);
         fq[d][0] = q0 * g00 + q1 * g10 + q2 * g20;
         fq[d][1] = q0 * g01 + q1 * g11 + q2 * g21;
-        fx[d][0] = x0 * g00 + x1 * g10 + x2 * g20;
-        fx[d][1] = x0 * g01 + x1 * g11 + x2 * g21;
       }
       TriProj<T> P;
       project_triangle<T, NEWTON>(fq, P, bad);
@@ -171,7 +165,7 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
       for (int d = 0; d < 3; ++d) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-          w[2 * d + k] = area * (ws * (ps[d][k] - fx[d][k]) + wa * (pa[d][k] - fx[d][k]));
+          w[2 * d + k] = area * (ws * (ps[d][k] - fq[d][k]) + wa * (pa[d][k] - fq[d][k]));
         }
       }
       if (want_energy) {
@@ -249,14 +243,16 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
     __syncthreads();
   }
 
-  // inertia term of the own vertices, loaded here so that the loads are in
-  // flight during the hinge phase (barriers wait for LDS only)
+  // inertia term of the own vertices, cterm - (m/h^2) delta, loaded here so
+  // that the loads are in flight during the hinge phase (barriers wait for
+  // LDS only)
+  const T mh2 = T(a.m / (a.h * a.h));
   T ct[VPT][3];
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
-    const int v = tid + j * BLOCK;
+    const int v = min(tid + j * BLOCK, N - 1);  // (rows past N are not stored)
 #pragma unroll
-    for (int d = 0; d < 3; ++d) ct[j][d] = v < N ? ccol[d * Npad + v] : T(0);
+    for (int d = 0; d < 3; ++d) ct[j][d] = ccol[d * Npad + v] - mh2 * dcol[d * Npad + v];
   }
 
   // ---- hinges: bending ----
@@ -271,20 +267,19 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
       if (e + BLOCK < base + ne) idn = cv.hin_v[e + BLOCK];
       const T k0 = r0.x, k1 = r0.y, k2 = r0.z, k3 = r0.w, ce = r1.x, rr = r1.y;
       const V4<T> qi = qs[id.x], qj = qs[id.y], qk = qs[id.z], ql = qs[id.w];
-      const V4<T> xi = xs[id.x], xj = xs[id.y], xk = xs[id.z], xl = xs[id.w];
-      T yq[3], yx[3];
+      T yq[3];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
+      for (int d = 0; d < 3; ++d)
         yq[d] = k0 * comp(qi, d) + k1 * comp(qj, d) + k2 * comp(qk, d) + k3 * comp(ql, d);
-        yx[d] = k0 * comp(xi, d) + k1 * comp(xj, d) + k2 * comp(xk, d) + k3 * comp(xl, d);
-      }
       const T n2 = yq[0] * yq[0] + yq[1] * yq[1] + yq[2] * yq[2];
       const T sc = n2 > T(0) ? rr * f_rcp(f_sqrt(n2)) : T(1);
       const T wc = wb * ce;
+      // w_b c_e (Pb - y(q)), Pb = sc y(q)
+      const T ws1 = wc * (sc - T(1));
       V4<T> y;
-      y.x = wc * (sc * yq[0] - yx[0]);
-      y.y = wc * (sc * yq[1] - yx[1]);
-      y.z = wc * (sc * yq[2] - yx[2]);
+      y.x = ws1 * yq[0];
+      y.y = ws1 * yq[1];
+      y.z = ws1 * yq[2];
       y.w = T(0);
       ys[e - base] = y;
       if (want_energy) {
@@ -354,7 +349,7 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
     __syncthreads();
   }
 
-  // ---- r = inertia + elastic contributions; zero padding rows ----
+  // ---- r = inertia - (m/h^2) delta + elastic contributions; zero padding rows ----
   float cmax[3] = {0.f, 0.f, 0.f};
   const double hm = a.h * a.h / a.m;
   const bool want_max = a.colmax != nullptr;
@@ -366,11 +361,11 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
       for (int d = 0; d < 3; ++d) {
         T r = T(0);
         if (v < N) {
-          const T c = ct[j < VPT ? j : VPT - 1][d];
-          r = c + acc[j < VPT ? j : VPT - 1][d];
+          const int jj = j < VPT ? j : VPT - 1;
+          r = ct[jj][d] + acc[jj][d];
           if (want_energy) {
             // (m/2h^2) |q - s|^2 with q - s = delta - (h^2/m) cterm
-            const double dd = (double)dcol[d * Npad + v] - hm * (double)c;
+            const double dd = (double)dcol[d * Npad + v] - hm * (double)ccol[d * Npad + v];
             e_acc += 0.5 * (a.m / (a.h * a.h)) * dd * dd;
           }
         }
@@ -398,12 +393,12 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
   if (__syncthreads_or(bad) && tid == 0) atomicOr(a.status, ST_NONFINITE);
 }
 
-// LDS: reductions, q and x as 4-component records, and a work region that
+// LDS: reductions, q as 4-component records (plus a zero record), and a work region that
 // holds the volume iterate p (N records plus a zero record) or one chunk of
 // triangle (6 values) or hinge (4 values) contributions.
 template <typename T>
 size_t local_smem_bytes_chunks(const ClassView<T>& cv, int block, int* tch, int* hch) {
-  const size_t fixed = 8 * sizeof(double) * (block / kWave) + sizeof(T) * 8 * (size_t)cv.N;
+  const size_t fixed = 8 * sizeof(double) * (block / kWave) + sizeof(T) * 4 * ((size_t)cv.N + 1);
   const size_t max_total = 160 * 1024;
   const size_t work_min = 4 * ((size_t)cv.N + 1);
   const size_t want = std::max<size_t>(6 * (size_t)cv.F, 4 * (size_t)cv.E);

@@ -67,7 +67,8 @@ __global__ void __launch_bounds__(256) update_kernel(ClassSlice<T> cs, T* __rest
   }
 }
 
-// Refinement residual res = r - A_c delta for each cell, with the per-cell
+// Refinement residual res = r - A_c (delta - delta0) for each cell (delta0 the
+// iterate the solve started from, nullptr for none), with the per-cell
 // system A_c = (m/h^2 + w_v) I + (w_s + w_a) L_tri + w_b L_bend (fixed-width
 // rows of the two Laplacians, shared by the class). One workgroup handles CPB
 // cells with one thread per row (up to 768 rows at a time): the row's table
@@ -90,7 +91,8 @@ constexpr int kResidualBlock = 768;
 
 template <typename T, int CPB>
 __global__ void __launch_bounds__(kResidualBlock) residual_kernel(
-    ClassSlice<T> cs, const T* __restrict__ rhs, const T* __restrict__ delta, T* __restrict__ res,
+    ClassSlice<T> cs, const T* __restrict__ rhs, const T* __restrict__ delta,
+    const T* __restrict__ delta0, T* __restrict__ res,
     const T* __restrict__ weights, float* __restrict__ colmax, const float* __restrict__ need,
     double need_factor, double need_thr, double h) {
   extern __shared__ double smem_res[];
@@ -116,6 +118,7 @@ __global__ void __launch_bounds__(kResidualBlock) residual_kernel(
     return;
   }
   const T* __restrict__ dcell = delta + cs.elem0 + 3LL * c0 * Npad;
+  const T* __restrict__ d0cell = delta0 ? delta0 + cs.elem0 + 3LL * c0 * Npad : nullptr;
   const T* __restrict__ rcell = rhs + cs.elem0 + 3LL * c0 * Npad;
   T* __restrict__ ocell = res + cs.elem0 + 3LL * c0 * Npad;
   const int* __restrict__ lcol = cs.cv.lap_col;
@@ -125,16 +128,20 @@ __global__ void __launch_bounds__(kResidualBlock) residual_kernel(
     const int v = v0 + tid;
     if (v <= N) {
       const int vc = min(v, N - 1);
-      T dv[CPB][3];
+      T dv[CPB][3], d0[CPB][3];
+#pragma unroll
+      for (int c = 0; c < CPB; ++c)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const size_t e = (size_t)(3 * min(c, ncell - 1) + d) * Npad + vc;
+          dv[c][d] = dcell[e];
+          d0[c][d] = d0cell ? d0cell[e] : T(0);
+        }
 #pragma unroll
       for (int c = 0; c < CPB; ++c)
 #pragma unroll
         for (int d = 0; d < 3; ++d)
-          dv[c][d] = dcell[(size_t)(3 * min(c, ncell - 1) + d) * Npad + vc];
-#pragma unroll
-      for (int c = 0; c < CPB; ++c)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) sd[(3 * c + d) * N1 + v] = (v < N && c < ncell) ? dv[c][d] : T(0);
+          sd[(3 * c + d) * N1 + v] = (v < N && c < ncell) ? dv[c][d] - d0[c][d] : T(0);
     }
   }
   if (tid < 3 * CPB) cmx[tid] = 0u;
@@ -272,16 +279,17 @@ static size_t residual_smem(int N) {
 // Cells per workgroup: the most (up to 6 in FP32, 4 in FP64) whose delta fits
 // 64 KB of LDS.
 template <typename T>
-hipError_t launch_residual(const ClassSlice<T>& cs, const T* rhs, const T* delta, T* res,
-                           const T* weights, float* colmax, const float* need, double need_factor,
-                           double need_thr, double h, hipStream_t st) {
+hipError_t launch_residual(const ClassSlice<T>& cs, const T* rhs, const T* delta,
+                           const T* delta0, T* res, const T* weights, float* colmax,
+                           const float* need, double need_factor, double need_thr, double h,
+                           hipStream_t st) {
   if (cs.n_cells == 0) return hipSuccess;
   const int N = cs.cv.N;
   const int block = std::min(kResidualBlock, (cs.cv.Npad + 63) / 64 * 64);
   const size_t cap = 64 * 1024;
   auto go = [&](auto kern, int cpb, size_t smem) {
     hipLaunchKernelGGL(kern, dim3((cs.n_cells + cpb - 1) / cpb), dim3(block), smem, st, cs, rhs,
-                       delta, res, weights, colmax, need, need_factor, need_thr, h);
+                       delta, delta0, res, weights, colmax, need, need_factor, need_thr, h);
     return hipGetLastError();
   };
   if constexpr (sizeof(T) == 4) {  // (6 FP64 cells would not fit the registers)
@@ -306,8 +314,8 @@ hipError_t launch_volume(const ClassSlice<T>& cs, const T* pos, long long sumN, 
                                         long long, T*, T*, int*, double, hipStream_t);           \
   template hipError_t launch_update<T>(const ClassSlice<T>&, T*, T*, long long, const T*, double, \
                                        hipStream_t);                                             \
-  template hipError_t launch_residual<T>(const ClassSlice<T>&, const T*, const T*, T*, const T*, \
-                                         float*, const float*, double, double, double,           \
+  template hipError_t launch_residual<T>(const ClassSlice<T>&, const T*, const T*, const T*, T*, \
+                                         const T*, float*, const float*, double, double, double, \
                                          hipStream_t);                                           \
   template hipError_t launch_volume<T>(const ClassSlice<T>&, const T*, long long, double*,       \
                                        hipStream_t);

@@ -108,6 +108,7 @@ struct npfem_batch_s {
   void* pos = nullptr;
   void* vel = nullptr;
   void* delta = nullptr;
+  void* delta2 = nullptr;  // the other iterate buffer (PD iterations alternate)
   void* cterm = nullptr;
   void* rhs = nullptr;
   void* res = nullptr;
@@ -588,11 +589,13 @@ int factorise(npfem_batch_s* b, double dt) {
     if (idx_ >= 0) b->ev_end(idx_, kind, st);                   \
   } while (0)
 
-// C = A_c^-1 B for one class: one GEMM with the stored class operator, then
-// the correction sweeps C += A_0^-1 (B - A_c C) (per-cell weights, low
-// precision). B and C are batch column buffers.
+// C = D + A_c^-1 B for one class (D = nullptr: none; D may be C): one GEMM
+// with the stored class operator, then the correction sweeps
+// C += A_0^-1 (B - A_c (C - D)) (per-cell weights, low precision). B, C and D
+// are batch column buffers.
 template <typename T>
-int enqueue_solve(npfem_batch_s* b, ClassState& c, T* B, T* C, double h, hipStream_t st) {
+int enqueue_solve(npfem_batch_s* b, ClassState& c, T* B, T* C, const T* D, double h,
+                  hipStream_t st) {
   T* res = static_cast<T*>(b->res);
   const T* w = b->per_cell ? static_cast<const T*>(b->weights_dev) : nullptr;
   const bool lp = b->gemm_kind >= 2;
@@ -601,6 +604,7 @@ int enqueue_solve(npfem_batch_s* b, ClassState& c, T* B, T* C, double h, hipStre
   g.A = c.op;
   g.B = B + c.elem0;
   g.C = C + c.elem0;
+  g.D = D ? D + c.elem0 : nullptr;
   g.colscale = colmax ? colmax + c.col0 : nullptr;
   g.Npad = c.Npad;
   g.ncols = 3 * c.n_cells;
@@ -618,7 +622,7 @@ int enqueue_solve(npfem_batch_s* b, ClassState& c, T* B, T* C, double h, hipStre
   for (int s = 0; s < b->n_refine; ++s) {
     bound *= b->rho;
     NPFEM_TIMED(NPFEM_KERNEL_RESIDUAL,
-                launch_residual<T>(slice_of<T>(c), B, C, res, w, lp ? b->colmax_res : nullptr,
+                launch_residual<T>(slice_of<T>(c), B, C, D, res, w, lp ? b->colmax_res : nullptr,
                                    adapt ? colmax : nullptr, bound,
                                    std::ldexp(1.0, -24) * c.r_rest, h, st),
                 "residual");
@@ -635,18 +639,24 @@ int enqueue_solve(npfem_batch_s* b, ClassState& c, T* B, T* C, double h, hipStre
 // (local step, global solve) iterations, update. dslots, if given, holds
 // n_iter + 1 column buffers: iterate k is read from dslots[k] and the solve
 // writes dslots[k + 1] (recording every PD iterate for the adjoint);
-// otherwise all iterates share the batch's delta buffer. Classes touch
+// otherwise the iterates alternate between the batch's two iterate buffers.
+// The solve of iteration k forms iterate k + 1 as iterate k plus
+// A^-1 (cterm - (m/h^2) delta_k + R(q_k)) (the local step's increment form,
+// see kernels_local.hip). Classes touch
 // disjoint parts of every batch buffer, so their chains are independent.
 template <typename T>
 int enqueue_class_step(npfem_batch_s* b, ClassState& c, T* pos, T* vel, const T* forces,
                        double h, int n_iter, hipStream_t st, T* const* dslots) {
   T* delta = static_cast<T*>(b->delta);
+  T* delta2 = static_cast<T*>(b->delta2);
   T* cterm = static_cast<T*>(b->cterm);
   T* rhs = static_cast<T*>(b->rhs);
   const T* w = b->per_cell ? static_cast<const T*>(b->weights_dev) : nullptr;
   float* colmax = (b->gemm_kind >= 2) ? b->colmax : nullptr;
   const bool want_energy = (b->flags & NPFEM_OPT_ENERGY) != 0 && !dslots;
-  auto slot = [&](int k) { return dslots ? dslots[k] : delta; };
+  // iterate k: dslots[k], else the two iterate buffers in turn (the solve
+  // reads iterate k and writes k + 1 = k + A^-1 r)
+  auto slot = [&](int k) { return dslots ? dslots[k] : (k & 1) ? delta2 : delta; };
   NPFEM_TIMED(NPFEM_KERNEL_PREDICT,
               launch_predict<T>(slice_of<T>(c), pos, vel, forces, b->sumN, slot(0), cterm,
                                 b->status, h, st),
@@ -668,7 +678,7 @@ int enqueue_class_step(npfem_batch_s* b, ClassState& c, T* pos, T* vel, const T*
     a.max_vol_iter = b->max_vol_iter;
     set_volume_tolerances(a, c, b->fp64);
     NPFEM_TIMED(NPFEM_KERNEL_LOCAL, launch_local<T>(a, c.local_block, st), "local step");
-    const int rc = enqueue_solve<T>(b, c, rhs, slot(it + 1), h, st);
+    const int rc = enqueue_solve<T>(b, c, rhs, slot(it + 1), slot(it), h, st);
     if (rc) return rc;
   }
   NPFEM_TIMED(NPFEM_KERNEL_UPDATE,
@@ -801,6 +811,9 @@ int autotune(npfem_batch_s* b, double h) {
     g.A = c.op;
     g.B = static_cast<T*>(b->rhs) + c.elem0;
     g.C = static_cast<T*>(b->delta) + c.elem0;
+    // (the step's solve adds the previous iterate; the other iterate buffer
+    // stands in for it, so that repeated trials do not accumulate)
+    g.D = static_cast<T*>(b->delta2) + c.elem0;
     g.colscale = nullptr;
     g.Npad = c.Npad;
     g.ncols = 3 * c.n_cells;
@@ -931,7 +944,7 @@ int adjoint_impl(npfem_batch_s* b, const void* dL_dx, const void* dL_dv, void* d
       for (int k = K - 1; k >= 0; --k) {
         for (auto& c : b->cls) {
           if (c.n_cells == 0) continue;
-          if ((rc = enqueue_solve<T>(b, c, gbar, lam, h, st))) return rc;
+          if ((rc = enqueue_solve<T>(b, c, gbar, lam, nullptr, h, st))) return rc;
           AdjArgs<T> a;
           a.cs = slice_of<T>(c);
           a.xn = tj;
@@ -1104,6 +1117,7 @@ int npfem_create_batch(const npfem_mesh* meshes, int32_t n_meshes, const int32_t
   if ((rc = apply_weights(b.get(), cell_weights))) return rc;
   const size_t colbytes = tsz * (size_t)b->total_elems;
   if ((rc = dalloc(b.get(), &b->delta, colbytes, "delta"))) return rc;
+  if ((rc = dalloc(b.get(), &b->delta2, colbytes, "delta2"))) return rc;
   if ((rc = dalloc(b.get(), &b->cterm, colbytes, "cterm"))) return rc;
   if ((rc = dalloc(b.get(), &b->rhs, colbytes, "rhs"))) return rc;
   if ((rc = dalloc(b.get(), &b->res, colbytes, "res"))) return rc;
@@ -1117,6 +1131,7 @@ int npfem_create_batch(const npfem_mesh* meshes, int32_t n_meshes, const int32_t
   if ((rc = dalloc(b.get(), &p, sizeof(double) * (size_t)n_cells, "volume"))) return rc;
   b->volume_buf = static_cast<double*>(p);
   HIP_TRY(hipMemset(b->delta, 0, colbytes), "memset");
+  HIP_TRY(hipMemset(b->delta2, 0, colbytes), "memset");
   HIP_TRY(hipMemset(b->rhs, 0, colbytes), "memset");
   HIP_TRY(hipMemset(b->res, 0, colbytes), "memset");
   HIP_TRY(hipMemset(b->cterm, 0, colbytes), "memset");

@@ -103,6 +103,7 @@ struct GemmArgs {
   const void* A;       // [Npad][Npad] symmetric operator (element type per kernel)
   const void* B;       // input columns [ncols][Npad] (float or double)
   void* C;             // output columns [ncols][Npad]
+  const void* D = nullptr;  // SET modes: columns added to the product (may be C), or nullptr
   const float* colscale;  // per-column scale of B for low-precision operands, or nullptr
   int Npad;
   int ncols;
@@ -128,9 +129,10 @@ size_t local_smem_bytes(const ClassView<T>& cv, int block);
 template <typename T>
 hipError_t local_prepare(const ClassView<T>& cv, int block);
 template <typename T>
-hipError_t launch_residual(const ClassSlice<T>& cs, const T* rhs, const T* delta, T* res,
-                           const T* weights, float* colmax, const float* need, double need_factor,
-                           double need_thr, double h, hipStream_t st);
+hipError_t launch_residual(const ClassSlice<T>& cs, const T* rhs, const T* delta,
+                           const T* delta0, T* res, const T* weights, float* colmax,
+                           const float* need, double need_factor, double need_thr, double h,
+                           hipStream_t st);
 template <typename T>
 hipError_t launch_volume(const ClassSlice<T>& cs, const T* pos, long long sumN, double* out,
                          hipStream_t st);
