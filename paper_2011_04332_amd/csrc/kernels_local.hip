@@ -41,8 +41,9 @@ struct LocalLaunch {
 };
 
 // KT, KH > 0: compile-time incidence widths (triangles and hinges per
-// vertex; they must equal cv.DT and cv.DH), so that every incidence entry of
-// a vertex is fetched in one memory round trip before the gathers use them.
+// vertex; they must equal cv.DT and cv.DH, and the class must have its
+// one-rings, cv.vt_ring), so that every incidence entry of a vertex is
+// fetched in one memory round trip before the gathers use them.
 // 0: widths read at run time.
 // Occupancy target (waves per SIMD) for FP32, which sets the register
 // budget: with 256 threads the LDS of a 642-vertex cell allows three
@@ -427,19 +428,20 @@ using LocalFn = void (*)(LocalLaunch<T>);
 constexpr int kFixedDT = 6, kFixedDH = 12;
 
 template <typename T, int BLOCK, int VPT>
-static LocalFn<T> pick_widths(int DT, int DH) {
-  if (DT == kFixedDT && DH == kFixedDH) return local_kernel<T, BLOCK, VPT, kFixedDT, kFixedDH>;
+static LocalFn<T> pick_widths(int DT, int DH, bool ring) {
+  if (DT == kFixedDT && DH == kFixedDH && ring)
+    return local_kernel<T, BLOCK, VPT, kFixedDT, kFixedDH>;
   return local_kernel<T, BLOCK, VPT, 0, 0>;
 }
 
 template <typename T, int BLOCK>
-static LocalFn<T> pick_vpt(int N, int DT, int DH) {
+static LocalFn<T> pick_vpt(int N, int DT, int DH, bool ring) {
   const int vpt = (N + BLOCK - 1) / BLOCK;
-  if (vpt <= 1) return pick_widths<T, BLOCK, 1>(DT, DH);
-  if (vpt <= 2) return pick_widths<T, BLOCK, 2>(DT, DH);
-  if (vpt <= 3) return pick_widths<T, BLOCK, 3>(DT, DH);
-  if (vpt <= 4) return pick_widths<T, BLOCK, 4>(DT, DH);
-  if (vpt <= 6) return pick_widths<T, BLOCK, 6>(DT, DH);
+  if (vpt <= 1) return pick_widths<T, BLOCK, 1>(DT, DH, ring);
+  if (vpt <= 2) return pick_widths<T, BLOCK, 2>(DT, DH, ring);
+  if (vpt <= 3) return pick_widths<T, BLOCK, 3>(DT, DH, ring);
+  if (vpt <= 4) return pick_widths<T, BLOCK, 4>(DT, DH, ring);
+  if (vpt <= 6) return pick_widths<T, BLOCK, 6>(DT, DH, ring);
   if (vpt <= 8) return local_kernel<T, BLOCK, 8, 0, 0>;
   if (vpt <= 11) return local_kernel<T, BLOCK, 11, 0, 0>;
   return nullptr;
@@ -448,9 +450,9 @@ static LocalFn<T> pick_vpt(int N, int DT, int DH) {
 template <typename T>
 static LocalFn<T> pick_local(const ClassView<T>& cv, int block) {
   switch (block) {
-    case 128: return pick_vpt<T, 128>(cv.N, cv.DT, cv.DH);
-    case 256: return pick_vpt<T, 256>(cv.N, cv.DT, cv.DH);
-    case 512: return pick_vpt<T, 512>(cv.N, cv.DT, cv.DH);
+    case 128: return pick_vpt<T, 128>(cv.N, cv.DT, cv.DH, cv.vt_ring != nullptr);
+    case 256: return pick_vpt<T, 256>(cv.N, cv.DT, cv.DH, cv.vt_ring != nullptr);
+    case 512: return pick_vpt<T, 512>(cv.N, cv.DT, cv.DH, cv.vt_ring != nullptr);
     default: return nullptr;
   }
 }

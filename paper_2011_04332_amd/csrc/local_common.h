@@ -64,15 +64,20 @@ __device__ __forceinline__ void volume_gradient(const ClassView<T>& cv, const V4
   gz *= T(1.0 / 6.0);
 }
 
-// The same sum from fan indices already in registers.
+// The same sum from the one-ring n_0 .. n_{KT-1} (indices in registers; a
+// ring shorter than KT is padded with n_0, whose terms n_0 x n_0 vanish):
+// (1/6) sum_k n_k x n_{k+1 mod KT}, one LDS record per neighbour.
 template <typename T, int KT>
-__device__ __forceinline__ void volume_gradient_fan(const V4<T>* ps, const int (&bc)[KT], T& gx,
-                                                    T& gy, T& gz) {
+__device__ __forceinline__ void volume_gradient_ring(const V4<T>* ps, const int (&r)[KT], T& gx,
+                                                     T& gy, T& gz) {
+  V4<T> p[KT];
+#pragma unroll
+  for (int u = 0; u < KT; ++u) p[u] = ps[r[u]];
   gx = gy = gz = T(0);
 #pragma unroll
   for (int u = 0; u < KT; ++u) {
-    const V4<T> pb = ps[bc[u] & 0xffff];
-    const V4<T> pc = ps[bc[u] >> 16];
+    const V4<T>& pb = p[u];
+    const V4<T>& pc = p[(u + 1) % KT];
     gx += pb.y * pc.z - pb.z * pc.y;
     gy += pb.z * pc.x - pb.x * pc.z;
     gz += pb.x * pc.y - pb.y * pc.x;
@@ -101,7 +106,8 @@ __device__ __forceinline__ void volume_gradient_fan(const V4<T>* ps, const int (
 // produced p (p = q + lam g), and the value is lam. With STORE_P, ps[0..N)
 // also holds p and ps[N] = 0, behind a barrier. Without it, ps is scratch
 // (written only when a second iteration runs) and no thread reads it any
-// more. red: 8 * (BLOCK / 64) doubles. KT: fan width (0 = runtime). Call
+// more. red: 8 * (BLOCK / 64) doubles. KT: fan width (0 = runtime; > 0
+// needs cv.vt_ring, whose rings it reads instead of the fan pairs). Call
 // from uniform control flow.
 template <typename T, int BLOCK, int VPT, bool STORE_P, int KT = 0>
 __device__ double volume_project(const ClassView<T>& cv, const V4<T>* qs, V4<T>* ps, double* red,
@@ -114,7 +120,7 @@ __device__ double volume_project(const ClassView<T>& cv, const V4<T>* qs, V4<T>*
   for (int it = 0; it < max_it; ++it) {
     double s[3] = {0.0, 0.0, 0.0};
     double mq = 0.0;
-    // KT > 0: the fan indices of all of this thread's vertices are fetched
+    // KT > 0: the ring indices of all of this thread's vertices are fetched
     // in one round trip up front
     int fan[VPT][KT > 0 ? KT : 1];
     if constexpr (KT > 0) {
@@ -122,7 +128,7 @@ __device__ double volume_project(const ClassView<T>& cv, const V4<T>* qs, V4<T>*
       for (int j = 0; j < VPT; ++j) {
         const int v = min(tid + j * BLOCK, N - 1);
 #pragma unroll
-        for (int u = 0; u < KT; ++u) fan[j][u] = cv.vt_fan[v * KT + u];
+        for (int u = 0; u < KT; ++u) fan[j][u] = cv.vt_ring[v * KT + u];
       }
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -133,7 +139,7 @@ __device__ double volume_project(const ClassView<T>& cv, const V4<T>* qs, V4<T>*
       if (v < N) {
         T gx, gy, gz;
         if constexpr (KT > 0) {
-          volume_gradient_fan<T, KT>(src, fan[j], gx, gy, gz);
+          volume_gradient_ring<T, KT>(src, fan[j], gx, gy, gz);
         } else {
           volume_gradient<T, 0>(cv, src, v, gx, gy, gz);
         }

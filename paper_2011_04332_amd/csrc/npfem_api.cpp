@@ -321,6 +321,35 @@ int upload_class(ClassState& c) {
   if ((rc = upload_vec(c, pt_tri, &v[5], "vt_tri"))) return rc;
   if ((rc = upload_vec(c, pt_g, &v[6], "vt_g"))) return rc;
   if ((rc = upload_vec(c, pt_fan, &v[7], "vt_fan"))) return rc;
+  // one-ring in fan order, when every vertex's fan closes into a single cycle
+  // of distinct neighbours (closed manifold): the volume gradient then reads
+  // each neighbour once, (1/6) sum_k n_k x n_k+1
+  {
+    std::vector<int> pt_ring((size_t)c.DT * N, 0);
+    bool ok = c.DT >= 3;
+    for (int i = 0; i < N && ok; ++i) {
+      const int e0 = M.vt_ptr[i], deg = M.vt_ptr[i + 1] - e0;
+      int* ring = &pt_ring[(size_t)i * c.DT];
+      if (deg < 3) {
+        ok = false;
+        break;
+      }
+      ring[0] = M.vt_fan[e0] & 0xffff;
+      int cur = M.vt_fan[e0] >> 16;
+      for (int k = 1; k < deg && ok; ++k) {
+        for (int j = 0; j < k; ++j) ok = ok && ring[j] != cur;
+        ring[k] = cur;
+        int nxt = -1;
+        for (int e = e0; e < e0 + deg; ++e)
+          if ((M.vt_fan[e] & 0xffff) == cur) nxt = M.vt_fan[e] >> 16;
+        ok = ok && nxt >= 0;
+        cur = nxt;
+      }
+      ok = ok && cur == ring[0];
+      for (int k = deg; k < c.DT; ++k) ring[k] = ring[0];
+    }
+    if (ok && (rc = upload_vec(c, pt_ring, &v[8], "vt_ring"))) return rc;
+  }
   if ((rc = upload_vec(c, ph_hin, &v[9], "vh_hin"))) return rc;
   if ((rc = upload_vec(c, ph_k, &v[10], "vh_k"))) return rc;
   c.DL = 0;
@@ -358,6 +387,7 @@ ClassSlice<T> slice_of(const ClassState& c) {
   v.vt_tri = (const int*)c.view_ptrs[5];
   v.vt_g = (const T*)c.view_ptrs[6];
   v.vt_fan = (const int*)c.view_ptrs[7];
+  v.vt_ring = (const int*)c.view_ptrs[8];
   v.vh_hin = (const int*)c.view_ptrs[9];
   v.vh_k = (const T*)c.view_ptrs[10];
   v.DL = c.DL;

@@ -29,6 +29,9 @@ struct ClassView {
   const T* vt_g;       // [N][DT][2] G row of the vertex in that triangle (0 in padding)
   const int* vt_fan;   // [N][DT] other two vertices b | c << 16, (v, b, c) counter-clockwise;
                        // padding N | N << 16 (a zero record in the kernel's LDS)
+  const int* vt_ring;  // [N][DT] the one-ring n_0 .. n_{d-1} in fan order (the fan
+                       // triangles are (v, n_k, n_k+1 mod d)), padded with n_0; nullptr
+                       // unless every vertex's fan closes into one cycle
   const int* vh_hin;   // [N][DH] hinge index (0 in padding)
   const T* vh_k;       // [N][DH] stencil coefficient of the vertex (0 in padding)
   // Rows of the two Laplacians on their joint pattern (diagonal included),
