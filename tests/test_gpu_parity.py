@@ -110,6 +110,48 @@ def test_mixed_precision_refined(prec):
     assert err <= TOL[prec]
 
 
+def test_mixed_precision_sweeps_skipped_on_lattice():
+    """16-bit global step with the automatic sweep count on lattice cells
+    (uniform weights, dt 1e-4): the a-priori bound on the product's error is
+    below the FP32 rounding of the coordinates for every cell, so the sweeps
+    are skipped on the device. Results equal a run pinned to 0 sweeps bitwise,
+    and the error against the oracle stays at the FP32 run's level."""
+    s = as_precision(W.rbc_lattice(n_cells=64, n_steps=5), np.float32)
+    cells = [0, 37, 63]
+    ref = oracle_cells(s, cells)
+    x32, _ = run_gpu(s, "fp32")
+    err32 = max_error(s, x32, ref)
+    for prec in ("fp16", "bf16"):
+        log(f"lattice {prec} automatic sweeps")
+        x_auto, _ = run_gpu(s, prec)
+        x_none, _ = run_gpu(s, prec, n_refine=0)
+        assert np.array_equal(x_auto, x_none)
+        err = max_error(s, x_auto, ref)
+        log(f"lattice {prec} err {err:.3e} (fp32 {err32:.3e})")
+        assert err <= max(2.0 * err32, 2e-7)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_mixed_precision_uneven_adaptive(prec):
+    """Per-cell weights (+-20 %) make the shared class operator inexact for
+    every cell. At dt 1e-4 the mass term dominates A and the a-priori bound
+    lets the device skip the correction; on the stiff twin (dt 1e-2) it must
+    not: the sweeps run (the result differs from a run without them). Both
+    match the oracle within the reduced-precision bound."""
+    cells = [0, 19, 20, 31, 32, 34]
+    for stiff in (False, True):
+        s = W.uneven(n_rbc=20, n_plt=12, n_large=3, n_steps=3)
+        s = as_precision(W.stiff(s) if stiff else s, np.float32)
+        log(f"uneven {prec} stiff={stiff} automatic sweeps")
+        x_auto, _ = run_gpu(s, prec, autotune=True)
+        if stiff:
+            x_none, _ = run_gpu(s, prec, n_refine=0)
+            assert not np.array_equal(x_auto, x_none)
+        err = max_error(s, x_auto, oracle_cells(s, cells))
+        log(f"uneven {prec} stiff={stiff} err {err:.3e}")
+        assert err <= TOL[prec]
+
+
 # every global-step kernel shape (13 tiled shapes, then the column-stationary
 # kernel, reported with tile rows 0), forced through set_config
 GEMM_SHAPES = [(64, 64), (64, 128), (128, 64), (128, 128), (96, 64), (96, 128), (224, 32),
