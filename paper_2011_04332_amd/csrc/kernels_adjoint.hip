@@ -108,8 +108,9 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
     V4<T>* ps = reinterpret_cast<V4<T>*>(work);  // N + 1 records
     V4<T>* gs = ps + N + 1;                      // N + 1 records
     T g[VPT][3], pv[VPT][3];
+    const int no_ring[VPT][1] = {};
     const double mu = volume_project<T, BLOCK, VPT, true>(cv, qs, ps, red, g, pv, a.max_vol_iter,
-                                                          a.vol_tol, a.vol_abs, bad);
+                                                          a.vol_tol, a.vol_abs, bad, no_ring);
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;

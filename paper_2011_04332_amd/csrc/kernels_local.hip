@@ -101,6 +101,10 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
   double e_acc = 0.0;
   int bad = 0;
 
+  // the volume gradient's ring indices, requested while q is staged
+  int ring[VPT][KT > 0 ? KT : 1];
+  if constexpr (KT > 0) ring_indices<T, BLOCK, VPT, KT>(cv, ring);
+
   // ---- stage q = x + delta ----
   for (int v = tid; v < N; v += BLOCK)
     qs[v] = V4<T>{px[v] + dcol[v], py[v] + dcol[Npad + v], pz[v] + dcol[2 * Npad + v], T(0)};
@@ -117,20 +121,21 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
   {
     V4<T>* ps = reinterpret_cast<V4<T>*>(work);
     T g[VPT][3], p[VPT][3];
-    volume_project<T, BLOCK, VPT, false, KT>(cv, qs, ps, red, g, p, a.max_vol_iter, a.vol_tol,
-                                             a.vol_abs, bad);
+    const double lam = volume_project<T, BLOCK, VPT, false, KT>(
+        cv, qs, ps, red, g, p, a.max_vol_iter, a.vol_tol, a.vol_abs, bad, ring);
+    // w_v (Pv - q) with Pv - q = lam g
+    const T wl = wv * T(lam);
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
       if (v < N) {
-        const V4<T> q = qs[v];
-        acc[j][0] += wv * (p[j][0] - q.x);
-        acc[j][1] += wv * (p[j][1] - q.y);
-        acc[j][2] += wv * (p[j][2] - q.z);
+        acc[j][0] += wl * g[j][0];
+        acc[j][1] += wl * g[j][1];
+        acc[j][2] += wl * g[j][2];
         if (want_energy) {
-          const double d0 = (double)q.x - p[j][0], d1 = (double)q.y - p[j][1],
-                       d2 = (double)q.z - p[j][2];
-          e_acc += 0.5 * (double)wv * (d0 * d0 + d1 * d1 + d2 * d2);
+          const double g2 = (double)g[j][0] * g[j][0] + (double)g[j][1] * g[j][1] +
+                            (double)g[j][2] * g[j][2];
+          e_acc += 0.5 * (double)wv * lam * lam * g2;
         }
       }
     }

@@ -102,17 +102,30 @@ __device__ __forceinline__ void volume_gradient_ring(const V4<T>* ps, const int 
 // a sum of two cross-product matrices (1/6)[q_u]x, and g^T H g does not
 // change under translation). The test takes twice that bound.
 //
-// On return pv holds p for this thread's vertices, g the gradient that
-// produced p (p = q + lam g), and the value is lam. With STORE_P, ps[0..N)
-// also holds p and ps[N] = 0, behind a barrier. Without it, ps is scratch
-// (written only when a second iteration runs) and no thread reads it any
-// more. red: 8 * (BLOCK / 64) doubles. KT: fan width (0 = runtime; > 0
-// needs cv.vt_ring, whose rings it reads instead of the fan pairs). Call
-// from uniform control flow.
+// On return g holds the gradient that produced p (p = q + lam g) for this
+// thread's vertices and the value is lam. With STORE_P, pv holds p and
+// ps[0..N) too, with ps[N] = 0, behind a barrier. Without it, pv is left
+// unset (the caller takes p - q = lam g, which is also exact where the
+// rounded p - q is not), ps is scratch (written only when a second iteration
+// runs) and no thread reads it any more. red: 8 * (BLOCK / 64) doubles. KT:
+// fan width (0 = runtime; > 0 needs cv.vt_ring, whose rings the caller
+// fetches into ring with ring_indices, before it needs them). Call from
+// uniform control flow.
+template <typename T, int BLOCK, int VPT, int KT>
+__device__ __forceinline__ void ring_indices(const ClassView<T>& cv, int (&ring)[VPT][KT]) {
+#pragma unroll
+  for (int j = 0; j < VPT; ++j) {
+    const int v = min((int)threadIdx.x + j * BLOCK, cv.N - 1);
+#pragma unroll
+    for (int u = 0; u < KT; ++u) ring[j][u] = cv.vt_ring[v * KT + u];
+  }
+}
+
 template <typename T, int BLOCK, int VPT, bool STORE_P, int KT = 0>
 __device__ double volume_project(const ClassView<T>& cv, const V4<T>* qs, V4<T>* ps, double* red,
                                  T (&g)[VPT][3], T (&pv)[VPT][3], int max_it, double vol_tol,
-                                 double vol_abs, int& bad) {
+                                 double vol_abs, int& bad,
+                                 const int (&fan)[VPT][KT > 0 ? KT : 1]) {
   const int N = cv.N, tid = threadIdx.x;
   const V4<T>* src = qs;  // current iterate p
   double lam = 0.0;
@@ -120,18 +133,6 @@ __device__ double volume_project(const ClassView<T>& cv, const V4<T>* qs, V4<T>*
   for (int it = 0; it < max_it; ++it) {
     double s[3] = {0.0, 0.0, 0.0};
     double mq = 0.0;
-    // KT > 0: the ring indices of all of this thread's vertices are fetched
-    // in one round trip up front
-    int fan[VPT][KT > 0 ? KT : 1];
-    if constexpr (KT > 0) {
-#pragma unroll
-      for (int j = 0; j < VPT; ++j) {
-        const int v = min(tid + j * BLOCK, N - 1);
-#pragma unroll
-        for (int u = 0; u < KT; ++u) fan[j][u] = cv.vt_ring[v * KT + u];
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    }
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
@@ -146,8 +147,8 @@ __device__ double volume_project(const ClassView<T>& cv, const V4<T>* qs, V4<T>*
         g[j][0] = gx;
         g[j][1] = gy;
         g[j][2] = gz;
-        const V4<T> p = src[v];
         const V4<T> q = qs[v];
+        const V4<T> p = it == 0 ? q : src[v];
         s[0] += (double)(p.x * gx + p.y * gy + p.z * gz);
         s[1] += (double)(gx * gx + gy * gy + gz * gz);
         if (it > 0) s[2] += (double)(gx * (q.x - p.x) + gy * (q.y - p.y) + gz * (q.z - p.z));
@@ -162,15 +163,6 @@ __device__ double volume_project(const ClassView<T>& cv, const V4<T>* qs, V4<T>*
       bad = 1;
       lam_new = 0.0;
     }
-    const T lt = T(lam_new);
-#pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-      const int v = tid + j * BLOCK;
-      const V4<T> q = v < N ? qs[v] : V4<T>{T(0), T(0), T(0), T(0)};
-      pv[j][0] = q.x + lt * g[j][0];
-      pv[j][1] = q.y + lt * g[j][1];
-      pv[j][2] = q.z + lt * g[j][2];
-    }
     const double gn = sqrt(s[1]);
     const double allow = fmax(vol_tol * fabs(lam_new) * gn, vol_abs);
     bool conv;
@@ -184,9 +176,14 @@ __device__ double volume_project(const ClassView<T>& cv, const V4<T>* qs, V4<T>*
     const bool last = conv || it + 1 == max_it;
     if (last && !STORE_P) break;
     // publish p for the next iteration's gradient (or for the caller)
+    const T lt = T(lam_new);
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
+      const V4<T> q = v < N ? qs[v] : V4<T>{T(0), T(0), T(0), T(0)};
+      pv[j][0] = q.x + lt * g[j][0];
+      pv[j][1] = q.y + lt * g[j][1];
+      pv[j][2] = q.z + lt * g[j][2];
       if (v < N) ps[v] = V4<T>{pv[j][0], pv[j][1], pv[j][2], T(0)};
     }
     if (!stored && tid == 0) ps[N] = V4<T>{T(0), T(0), T(0), T(0)};
