@@ -65,6 +65,13 @@ __device__ __forceinline__ void xcd_tile(int& mt, int& nt) {
   nt = logical / nbx;
 }
 
+// Accumulating (correction) products of FP32/FP64 columns may come with
+// per-column maxima of the input (GemmArgs::colscale): a zero marks a column
+// that needs no correction, which is then neither computed into nor stored.
+__device__ __forceinline__ bool col_dead(const GemmArgs& g, int n) {
+  return g.mode == EPI_ADD && g.colscale && g.colscale[n] == 0.0f;
+}
+
 // ---------------------------------------------------------------- FP32/FP64
 template <typename T, int BM, int BN>
 __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 1)) gemm_kernel(GemmArgs g) {
@@ -90,6 +97,11 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 1)) gemm_kernel(Gem
   const int m0 = mt * BM, n0 = nt * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
+  if (g.mode == EPI_ADD && g.colscale) {  // a tile with no live column returns
+    bool live = false;
+    for (int j = tid; j < BN; j += 256) live = live || (n0 + j < ncols && !col_dead(g, n0 + j));
+    if (!__syncthreads_or(live)) return;
+  }
 
   Vec ra[NA], rb[NB];
   auto load_tiles = [&](int k0) {
@@ -180,7 +192,7 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 1)) gemm_kernel(Gem
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int n = n0 + wn * WN + j * 16 + (lane & 15);
-      if (n >= ncols) continue;
+      if (n >= ncols || col_dead(g, n)) continue;
       T* c = C + (size_t)n * Npad + mb;
       if (Dadd) {
         const T* d = Dadd + (size_t)n * Npad + mb;
@@ -399,7 +411,8 @@ __host__ __device__ inline int rs_k32(int npad) { return (npad + 31) / 32 * 32; 
 template <int NR, int NGU>
 __device__ __forceinline__ void rs_rows_f32(const float* __restrict__ A, const float* Bs, int Npad,
                                             int rb, int g0, float* __restrict__ C, int n0,
-                                            int ncols, const float* Dadd, int lane) {
+                                            int ncols, const float* Dadd, const GemmArgs& g,
+                                            int lane) {
   constexpr int NJ = (NR * NGU == 1) ? 4 : 1;
   constexpr int D = 4;  // prefetch distance in 16-k groups
   floatx4 acc[NR][NGU][NJ];
@@ -493,7 +506,7 @@ __device__ __forceinline__ void rs_rows_f32(const float* __restrict__ A, const f
 #pragma unroll
       for (int j = 1; j < NJ; ++j) acc[r][u][0] += acc[r][u][j];
       const int n = n0 + (g0 + u) * 16 + (lane & 15);
-      if (n >= ncols) continue;
+      if (n >= ncols || col_dead(g, n)) continue;
       float4* c =
           reinterpret_cast<float4*>(C + (size_t)n * Npad + (rb + r) * 16 + 4 * (lane >> 4));
       const float4 v{acc[r][u][0][0], acc[r][u][0][1], acc[r][u][0][2], acc[r][u][0][3]};
@@ -519,6 +532,11 @@ __global__ void __launch_bounds__(256) gemm_rs_f32_kernel(GemmArgs g) {
   const int Npad = g.Npad, ncols = g.ncols;
   const int n0 = blockIdx.x * RS_BN;
   const int tid = threadIdx.x;
+  if (g.mode == EPI_ADD && g.colscale) {  // no live column: nothing to do
+    bool live = false;
+    for (int j = tid; j < RS_BN; j += 256) live = live || (n0 + j < ncols && !col_dead(g, n0 + j));
+    if (!__syncthreads_or(live)) return;
+  }
   // staging, column index fastest (consecutive threads write consecutive
   // records); 8 loads per thread in flight at a time (clamped addresses,
   // values outside the matrix replaced by zeros, no branches)
@@ -556,10 +574,11 @@ __global__ void __launch_bounds__(256) gemm_rs_f32_kernel(GemmArgs g) {
   const float* Dadd = g.mode == EPI_ADD ? C : static_cast<const float*>(g.D);
   for (int i = 2 * wave; i < full; i += 8) {
     const int rb = i + rot < full ? i + rot : i + rot - full;
-    rs_rows_f32<2, RS_NG>(A, rs_lds, Npad, rb, 0, C, n0, ncols, Dadd, lane);
+    rs_rows_f32<2, RS_NG>(A, rs_lds, Npad, rb, 0, C, n0, ncols, Dadd, g, lane);
   }
   for (int u = wave; u < (nrb - full) * RS_NG; u += 4)
-    rs_rows_f32<1, 1>(A, rs_lds, Npad, full + u / RS_NG, u % RS_NG, C, n0, ncols, Dadd, lane);
+    rs_rows_f32<1, 1>(A, rs_lds, Npad, full + u / RS_NG, u % RS_NG, C, n0, ncols, Dadd, g,
+                      lane);
 }
 
 // 16-bit version: the split operator Bt (16-bit, [Npad][Npad]) against the

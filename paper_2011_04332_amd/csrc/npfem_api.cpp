@@ -572,11 +572,14 @@ int factorise(npfem_batch_s* b, double dt) {
     const double hm = dt * dt / c.mat.vertex_mass;
     c.beta = 0.0;
     c.kappa = 0.0;
-    if (b->gemm_kind >= 2) {
-      e = launch_max_abs_split(dA, c.N, c.Npad, hm, dbeta, nullptr);
-      if (e == hipSuccess) e = hipMemcpy(&c.beta, dbeta, sizeof(double), hipMemcpyDeviceToHost);
+    if (b->gemm_kind != 1) {
+      if (b->gemm_kind >= 2) {
+        e = launch_max_abs_split(dA, c.N, c.Npad, hm, dbeta, nullptr);
+        if (e == hipSuccess) e = hipMemcpy(&c.beta, dbeta, sizeof(double), hipMemcpyDeviceToHost);
+      }
       // kappa = max_i sum_j |Ainv_ij - hm delta_ij| / hm: the size of the part
-      // of the operator that passes through the 16-bit product
+      // of the operator that passes through the 16-bit product; with it,
+      // |A^-1|_inf <= hm (1 + kappa) bounds the solve for the sweep test
       if (e == hipSuccess)
         e = hipMemcpy(hA.data(), dA, sizeof(double) * hA.size(), hipMemcpyDeviceToHost);
       if (e != hipSuccess) {
@@ -619,17 +622,26 @@ int factorise(npfem_batch_s* b, double dt) {
     if (idx_ >= 0) b->ev_end(idx_, kind, st);                   \
   } while (0)
 
+// Correction sweeps that a cell does not need are skipped on the device:
+// FP32 state (FP32 or 16-bit products) with the automatic count.
+bool sweeps_adaptive(const npfem_batch_s* b) {
+  return b->n_refine > 0 && b->n_refine_opt < 0 && !b->fp64;
+}
+
 // C = D + A_c^-1 B for one class (D = nullptr: none; D may be C): one GEMM
 // with the stored class operator, then the correction sweeps
 // C += A_0^-1 (B - A_c (C - D)) (per-cell weights, low precision). B, C and D
 // are batch column buffers.
 template <typename T>
 int enqueue_solve(npfem_batch_s* b, ClassState& c, T* B, T* C, const T* D, double h,
-                  hipStream_t st) {
+                  hipStream_t st, bool step_solve) {
   T* res = static_cast<T*>(b->res);
   const T* w = b->per_cell ? static_cast<const T*>(b->weights_dev) : nullptr;
   const bool lp = b->gemm_kind >= 2;
   float* colmax = lp ? b->colmax : nullptr;
+  // (only the step's own solves: the per-column maxima describe its
+  // right-hand side)
+  const bool adapt = step_solve && sweeps_adaptive(b);
   GemmArgs g;
   g.A = c.op;
   g.B = B + c.elem0;
@@ -642,23 +654,25 @@ int enqueue_solve(npfem_batch_s* b, ClassState& c, T* B, T* C, const T* D, doubl
   g.hm = h * h / c.mat.vertex_mass;
   g.beta = c.beta;
   NPFEM_TIMED(NPFEM_KERNEL_GLOBAL, launch_gemm(b->gemm_kind, c.gemm_tile, g, st), "global step");
-  // 16-bit products with the automatic sweep count: sweep s + 1 runs for a
-  // cell only while the bound rho^(s+1) |delta| on the error left in its delta
+  // FP32 state with the automatic sweep count: sweep s + 1 runs for a cell
+  // only while the bound rho^(s+1) |delta| on the error left in its delta
   // exceeds the FP32 rounding of the cell's coordinates (2^-24 of its rest
   // radius), with |delta| <= |A_c^-1| max |r| <= hm (1 + kappa) / (1 - rho_w)
-  // max |r|; the per-cell test runs on the device (residual step).
-  const bool adapt = lp && b->n_refine_opt < 0 && !b->fp64;
+  // max |r| (max |r| per column from the local step); the per-cell test runs
+  // on the device (residual step), which marks the columns that need no
+  // correction with a zero maximum.
   double bound = g.hm * (1.0 + c.kappa) / std::max(1e-300, 1.0 - b->rho_w);
   for (int s = 0; s < b->n_refine; ++s) {
     bound *= b->rho;
     NPFEM_TIMED(NPFEM_KERNEL_RESIDUAL,
-                launch_residual<T>(slice_of<T>(c), B, C, D, res, w, lp ? b->colmax_res : nullptr,
-                                   adapt ? colmax : nullptr, bound,
+                launch_residual<T>(slice_of<T>(c), B, C, D, res, w,
+                                   (lp || adapt) ? b->colmax_res : nullptr,
+                                   adapt ? b->colmax : nullptr, bound,
                                    std::ldexp(1.0, -24) * c.r_rest, h, st),
                 "residual");
     GemmArgs r = g;
     r.B = res + c.elem0;
-    r.colscale = lp ? b->colmax_res + c.col0 : nullptr;
+    r.colscale = (lp || adapt) ? b->colmax_res + c.col0 : nullptr;
     r.mode = lp ? EPI_SPLIT_ADD : EPI_ADD;
     NPFEM_TIMED(NPFEM_KERNEL_GLOBAL, launch_gemm(b->gemm_kind, c.gemm_tile, r, st), "refinement");
   }
@@ -682,7 +696,7 @@ int enqueue_class_step(npfem_batch_s* b, ClassState& c, T* pos, T* vel, const T*
   T* cterm = static_cast<T*>(b->cterm);
   T* rhs = static_cast<T*>(b->rhs);
   const T* w = b->per_cell ? static_cast<const T*>(b->weights_dev) : nullptr;
-  float* colmax = (b->gemm_kind >= 2) ? b->colmax : nullptr;
+  float* colmax = (b->gemm_kind >= 2 || sweeps_adaptive(b)) ? b->colmax : nullptr;
   const bool want_energy = (b->flags & NPFEM_OPT_ENERGY) != 0 && !dslots;
   // iterate k: dslots[k], else the two iterate buffers in turn (the solve
   // reads iterate k and writes k + 1 = k + A^-1 r)
@@ -708,7 +722,7 @@ int enqueue_class_step(npfem_batch_s* b, ClassState& c, T* pos, T* vel, const T*
     a.max_vol_iter = b->max_vol_iter;
     set_volume_tolerances(a, c, b->fp64);
     NPFEM_TIMED(NPFEM_KERNEL_LOCAL, launch_local<T>(a, c.local_block, st), "local step");
-    const int rc = enqueue_solve<T>(b, c, rhs, slot(it + 1), slot(it), h, st);
+    const int rc = enqueue_solve<T>(b, c, rhs, slot(it + 1), slot(it), h, st, true);
     if (rc) return rc;
   }
   NPFEM_TIMED(NPFEM_KERNEL_UPDATE,
@@ -974,7 +988,7 @@ int adjoint_impl(npfem_batch_s* b, const void* dL_dx, const void* dL_dv, void* d
       for (int k = K - 1; k >= 0; --k) {
         for (auto& c : b->cls) {
           if (c.n_cells == 0) continue;
-          if ((rc = enqueue_solve<T>(b, c, gbar, lam, nullptr, h, st))) return rc;
+          if ((rc = enqueue_solve<T>(b, c, gbar, lam, nullptr, h, st, false))) return rc;
           AdjArgs<T> a;
           a.cs = slice_of<T>(c);
           a.xn = tj;
