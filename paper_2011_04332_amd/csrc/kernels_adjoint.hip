@@ -280,7 +280,7 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
                 k3 * comp(ls[id.w], d);
       }
       const T n2 = yq[0] * yq[0] + yq[1] * yq[1] + yq[2] * yq[2];
-      const T in = n2 > T(0) ? f_rcp(f_sqrt(n2)) : T(0);
+      const T in = n2 > T(0) ? f_rsq(n2) : T(0);
       const T sc = n2 > T(0) ? rr * in : T(1);
       T eb = T(0);
 #pragma unroll

@@ -163,18 +163,19 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
         fq[d][1] = q0 * g01 + q1 * g11 + q2 * g21;
       }
       TriProj<T> P;
-      project_triangle<T, NEWTON>(fq, P, bad);
-      const T(&ps)[3][2] = P.ps;
-      const T(&pa)[3][2] = P.pa;
+      project_triangle<T, NEWTON, false>(fq, P, bad);
+      T wt[3][2];
+      triangle_force(fq, P, area, ws, wa, wt);
       T* w = work + 6 * (t - base);
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          w[2 * d + k] = area * (ws * (ps[d][k] - fq[d][k]) + wa * (pa[d][k] - fq[d][k]));
-        }
+        w[2 * d] = wt[d][0];
+        w[2 * d + 1] = wt[d][1];
       }
       if (want_energy) {
+        triangle_targets(fq, P);
+        const T(&ps)[3][2] = P.ps;
+        const T(&pa)[3][2] = P.pa;
         double es = 0.0, ea = 0.0;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -278,7 +279,7 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
       for (int d = 0; d < 3; ++d)
         yq[d] = k0 * comp(qi, d) + k1 * comp(qj, d) + k2 * comp(qk, d) + k3 * comp(ql, d);
       const T n2 = yq[0] * yq[0] + yq[1] * yq[1] + yq[2] * yq[2];
-      const T sc = n2 > T(0) ? rr * f_rcp(f_sqrt(n2)) : T(1);
+      const T sc = n2 > T(0) ? rr * f_rsq(n2) : T(1);
       const T wc = wb * ce;
       // w_b c_e (Pb - y(q)), Pb = sc y(q)
       const T ws1 = wc * (sc - T(1));

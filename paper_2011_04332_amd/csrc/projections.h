@@ -25,11 +25,21 @@ __device__ __forceinline__ float f_sqrt(float x) { return __builtin_amdgcn_sqrtf
 __device__ __forceinline__ double f_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float f_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double f_rcp(double x) { return 1.0 / x; }
+// 1 / sqrt(x): FP32 the hardware reciprocal square root (about 1 ulp), FP64
+// the correctly rounded square root and division.
+__device__ __forceinline__ float f_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double f_rsq(double x) { return 1.0 / sqrt(x); }
+
+template <typename T>
+struct TriProj;
+template <typename T>
+__device__ __forceinline__ void triangle_targets(const T (&f)[3][2], TriProj<T>& P);
 
 template <typename T>
 struct TriProj {
   T a, b, c;        // S = [[a, b], [b, c]]
   T I1, J, tau;     // invariants
+  T iJ;             // 1 / J
   T w00, w01, w11;  // W = S^{-1/2}
   T mu, om;         // area multiplier, 1 / (1 - mu^2)
   T m00, m01, m11;  // M
@@ -39,7 +49,11 @@ struct TriProj {
 
 // Newton steps for mu from the linearisation (1 - J)/I1 (exact to first
 // order in the strain): errors go ~e^2 -> e^4 -> e^8 ...
-template <typename T, int NEWTON>
+// TARGETS: also form P.ps and P.pa (the forward step applies W and M through
+// triangle_force instead). FP32 takes J and 1/J from one reciprocal square
+// root of |f0 x f1|^2, and 1/tau likewise; FP64 keeps square roots and
+// divisions.
+template <typename T, int NEWTON, bool TARGETS = true>
 __device__ __forceinline__ void project_triangle(const T (&f)[3][2], TriProj<T>& P, int& bad) {
   P.a = f[0][0] * f[0][0] + f[1][0] * f[1][0] + f[2][0] * f[2][0];
   P.b = f[0][0] * f[0][1] + f[1][0] * f[1][1] + f[2][0] * f[2][1];
@@ -48,10 +62,26 @@ __device__ __forceinline__ void project_triangle(const T (&f)[3][2], TriProj<T>&
   const T ny = f[2][0] * f[0][1] - f[0][0] * f[2][1];
   const T nz = f[0][0] * f[1][1] - f[1][0] * f[0][1];
   P.I1 = P.a + P.c;
-  P.J = f_sqrt(nx * nx + ny * ny + nz * nz);  // |f0 x f1| = sqrt(det S)
-  if (!(P.J > T(1e-12) * P.I1) || !isfinite(P.I1)) bad = 1;
-  P.tau = f_sqrt(P.I1 + T(2) * P.J);
-  const T iw = f_rcp(P.J * P.tau);
+  const T n2 = nx * nx + ny * ny + nz * nz;  // |f0 x f1|^2 = det S
+  T iJ, iw;
+  if constexpr (sizeof(T) == 4) {
+    iJ = f_rsq(n2);
+    P.J = n2 * iJ;
+    // (the test on n2 also catches a zero or denormal area, where
+    // the reciprocal square root is infinite)
+    if (!(n2 > T(1e-24) * P.I1 * P.I1) || !isfinite(P.I1)) bad = 1;
+    const T t2 = P.I1 + T(2) * P.J;
+    const T itau = f_rsq(t2);
+    P.tau = t2 * itau;
+    iw = iJ * itau;
+  } else {
+    P.J = f_sqrt(n2);
+    if (!(P.J > T(1e-12) * P.I1) || !isfinite(P.I1)) bad = 1;
+    P.tau = f_sqrt(P.I1 + T(2) * P.J);
+    iw = f_rcp(P.J * P.tau);
+    iJ = f_rcp(P.J);
+  }
+  P.iJ = iJ;
   P.w00 = (P.I1 + P.J - P.a) * iw;  // ((I1 + J) I - S) / (J tau)
   P.w01 = -P.b * iw;
   P.w11 = (P.I1 + P.J - P.c) * iw;
@@ -66,16 +96,38 @@ __device__ __forceinline__ void project_triangle(const T (&f)[3][2], TriProj<T>&
   P.mu = mu;
   P.om = f_rcp(T(1) - mu * mu);
   if (!isfinite(P.om)) bad = 1;
-  const T k = mu * f_rcp(P.J);  // M = (I + (mu/J) adj S)/(1 - mu^2), adj S = [[c, -b], [-b, a]]
+  const T k = mu * iJ;  // M = (I + (mu/J) adj S)/(1 - mu^2), adj S = [[c, -b], [-b, a]]
   P.m00 = (T(1) + k * P.c) * P.om;
   P.m01 = -k * P.b * P.om;
   P.m11 = (T(1) + k * P.a) * P.om;
+  if constexpr (TARGETS) triangle_targets(f, P);
+}
+
+template <typename T>
+__device__ __forceinline__ void triangle_targets(const T (&f)[3][2], TriProj<T>& P) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     P.ps[d][0] = f[d][0] * P.w00 + f[d][1] * P.w01;
     P.ps[d][1] = f[d][0] * P.w01 + f[d][1] * P.w11;
     P.pa[d][0] = f[d][0] * P.m00 + f[d][1] * P.m01;
     P.pa[d][1] = f[d][0] * P.m01 + f[d][1] * P.m11;
+  }
+}
+
+// The triangle's term of the local step, area (w_s (Ps - F) + w_a (Pa - F)),
+// as F Z with the symmetric 2x2 Z = area (w_s (W - I) + w_a (M - I)); M - I
+// in the cancellation-free form (mu^2 I + (mu/J) adj S) / (1 - mu^2).
+template <typename T>
+__device__ __forceinline__ void triangle_force(const T (&f)[3][2], const TriProj<T>& P, T area,
+                                               T ws, T wa, T (&w)[3][2]) {
+  const T k = P.mu * P.iJ * P.om, u = P.mu * P.mu * P.om;
+  const T z00 = area * (ws * (P.w00 - T(1)) + wa * fma(k, P.c, u));
+  const T z01 = area * (ws * P.w01 - wa * k * P.b);
+  const T z11 = area * (ws * (P.w11 - T(1)) + wa * fma(k, P.a, u));
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    w[d][0] = f[d][0] * z00 + f[d][1] * z01;
+    w[d][1] = f[d][0] * z01 + f[d][1] * z11;
   }
 }
 
