@@ -256,13 +256,32 @@ std::vector<T> cast_vec(const std::vector<double>& v) {
 template <typename T>
 int upload_class(ClassState& c) {
   const MeshOps& M = c.ops;
+  // Device triangle order: by first appearance in the vertex-major incidence
+  // lists, so that the triangles that consecutive vertices gather (the k-th
+  // of each) sit close together in LDS, which spreads one wave's reads over
+  // the banks. Only storage moves: each vertex still sums its triangles in
+  // ascending mesh order, so results do not depend on it.
+  std::vector<int> tord, tpos(M.F, -1);
+  tord.reserve(M.F);
+  for (int i = 0; i < M.N; ++i)
+    for (int e = M.vt_ptr[i]; e < M.vt_ptr[i + 1]; ++e)
+      if (tpos[M.vt_tri[e]] < 0) {
+        tpos[M.vt_tri[e]] = (int)tord.size();
+        tord.push_back(M.vt_tri[e]);
+      }
+  for (int t = 0; t < M.F; ++t)
+    if (tpos[t] < 0) {  // (a triangle no vertex lists: not on a valid mesh)
+      tpos[t] = (int)tord.size();
+      tord.push_back(t);
+    }
   std::vector<int> tri_v(4 * (size_t)M.F), hin_v(4 * (size_t)M.E);
   std::vector<T> tri_rec(8 * (size_t)M.F, T(0)), hin_rec(8 * (size_t)M.E, T(0));
-  for (int t = 0; t < M.F; ++t) {
-    for (int r = 0; r < 3; ++r) tri_v[4 * (size_t)t + r] = M.tris[3 * (size_t)t + r];
-    tri_v[4 * (size_t)t + 3] = 0;
-    for (int k = 0; k < 6; ++k) tri_rec[8 * (size_t)t + k] = T(M.G[6 * (size_t)t + k]);
-    tri_rec[8 * (size_t)t + 6] = T(M.area[t]);
+  for (int i = 0; i < M.F; ++i) {
+    const int t = tord[i];
+    for (int r = 0; r < 3; ++r) tri_v[4 * (size_t)i + r] = M.tris[3 * (size_t)t + r];
+    tri_v[4 * (size_t)i + 3] = 0;
+    for (int k = 0; k < 6; ++k) tri_rec[8 * (size_t)i + k] = T(M.G[6 * (size_t)t + k]);
+    tri_rec[8 * (size_t)i + 6] = T(M.area[t]);
   }
   for (int e = 0; e < M.E; ++e) {
     for (int r = 0; r < 4; ++r) {
@@ -303,7 +322,7 @@ int upload_class(ClassState& c) {
   for (int i = 0; i < N; ++i) {
     for (int e = M.vt_ptr[i], k = 0; e < M.vt_ptr[i + 1]; ++e, ++k) {
       const size_t s = (size_t)i * c.DT + k;
-      pt_tri[s] = M.vt_tri[e];
+      pt_tri[s] = tpos[M.vt_tri[e]];
       pt_fan[s] = M.vt_fan[e];
       pt_g[2 * s] = T(M.vt_g[2 * (size_t)e]);
       pt_g[2 * s + 1] = T(M.vt_g[2 * (size_t)e + 1]);
