@@ -407,8 +407,11 @@ __host__ __device__ inline int rs_k32(int npad) { return (npad + 31) / 32 * 32; 
 // and B alike, so one 16-byte load covers four sub-steps; every B fragment
 // read from LDS serves NR row blocks. With a single row block and column
 // group the four sub-steps accumulate separately (independent MFMA chains)
-// and are summed at the end.
-template <int NR, int NGU>
+// and are summed at the end. NIT >= 0: the main loop's trip count,
+// Npad / 16 / 8, fixed at compile time, so that it unrolls completely (with
+// a loop, the accumulators were rotated through extra registers at every
+// back edge); -1: read from Npad.
+template <int NR, int NGU, int NIT = -1>
 __device__ __forceinline__ void rs_rows_f32(const float* __restrict__ A, const float* Bs, int Npad,
                                             int rb, int g0, float* __restrict__ C, int n0,
                                             int ncols, const float* Dadd, const GemmArgs& g,
@@ -462,13 +465,14 @@ __device__ __forceinline__ void rs_rows_f32(const float* __restrict__ A, const f
       for (int u = 0; u < NGU; ++u)
         acc[r][u][3 % NJ] = Mfma4<float>::run(a[r].w, b[u].w, acc[r][u][3 % NJ]);
   };
-  // two register sets: the loads for the next D groups are issued (and kept
-  // ahead of the scheduler) before the current D groups are multiplied
-  float4 cur[D][NR], nxt[D][NR];
+  // two register sets that alternate: the loads for the next D groups go
+  // into one (issued, and kept ahead of the scheduler, before) while the
+  // other's D groups are multiplied; nothing is copied between them
+  float4 a0[D][NR], a1[D][NR];
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
-    for (int r = 0; r < NR; ++r) cur[i][r] = load_a(r, i);
+    for (int r = 0; r < NR; ++r) a0[i][r] = load_a(r, i);
   // the addend of the rows this lane stores, requested after the first
   // operator groups (so that their wait does not include it) and long before
   // the epilogue (clamped column index: columns past the last are never stored)
@@ -482,23 +486,44 @@ __device__ __forceinline__ void rs_rows_f32(const float* __restrict__ A, const f
                                                          4 * (lane >> 4))
                       : float4{0.f, 0.f, 0.f, 0.f};
     }
-  int kg = 0;
-  for (; kg + D <= nkg; kg += D) {
+  auto load_set = [&](float4(&dst)[D][NR], int kg0) {
 #pragma unroll
     for (int i = 0; i < D; ++i)
 #pragma unroll
-      for (int r = 0; r < NR; ++r) nxt[i][r] = load_a(r, kg + D + i);
+      for (int r = 0; r < NR; ++r) dst[i][r] = load_a(r, kg0 + i);
+  };
+  int kg = 0;
+  auto two_sets = [&](int k0) {
+    load_set(a1, k0 + D);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int i = 0; i < D; ++i) step(kg + i, cur[i]);
+    for (int i = 0; i < D; ++i) step(k0 + i, a0[i]);
+    load_set(a0, k0 + 2 * D);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) step(k0 + D + i, a1[i]);
+  };
+  if constexpr (NIT >= 0) {
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) two_sets(2 * D * it);
+    kg = 2 * D * NIT;
+  } else {
+    for (; kg + 2 * D <= nkg; kg += 2 * D) two_sets(kg);
+  }
+  // fewer than 2D groups left, the first D of them (clamped) in a0
+  if (kg + D < nkg) {
+    load_set(a1, kg + D);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) step(kg + i, a0[i]);
 #pragma unroll
     for (int i = 0; i < D; ++i)
+      if (kg + D + i < nkg) step(kg + D + i, a1[i]);
+  } else {
 #pragma unroll
-      for (int r = 0; r < NR; ++r) cur[i][r] = nxt[i][r];
+    for (int i = 0; i < D; ++i)
+      if (kg + i < nkg) step(kg + i, a0[i]);
   }
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-    if (i < nkg - kg) step(kg + i, cur[i]);
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
 #pragma unroll
@@ -572,9 +597,21 @@ __global__ void __launch_bounds__(256) gemm_rs_f32_kernel(GemmArgs g) {
   const int rot = full > 0 ? 2 * ((blockIdx.x / 8) % (full / 2)) : 0;
   // C = D + product (D = C when accumulating, none if null)
   const float* Dadd = g.mode == EPI_ADD ? C : static_cast<const float*>(g.D);
-  for (int i = 2 * wave; i < full; i += 8) {
-    const int rb = i + rot < full ? i + rot : i + rot - full;
-    rs_rows_f32<2, RS_NG>(A, rs_lds, Npad, rb, 0, C, n0, ncols, Dadd, g, lane);
+  auto pairs = [&](auto nit) {
+    for (int i = 2 * wave; i < full; i += 8) {
+      const int rb = i + rot < full ? i + rot : i + rot - full;
+      rs_rows_f32<2, RS_NG, decltype(nit)::value>(A, rs_lds, Npad, rb, 0, C, n0, ncols, Dadd, g,
+                                                  lane);
+    }
+  };
+  switch (nrb / 8) {  // main-loop trip count of rs_rows_f32
+    case 1: pairs(std::integral_constant<int, 1>{}); break;
+    case 2: pairs(std::integral_constant<int, 2>{}); break;
+    case 3: pairs(std::integral_constant<int, 3>{}); break;
+    case 4: pairs(std::integral_constant<int, 4>{}); break;
+    case 5: pairs(std::integral_constant<int, 5>{}); break;
+    case 6: pairs(std::integral_constant<int, 6>{}); break;
+    default: pairs(std::integral_constant<int, -1>{}); break;
   }
   for (int u = wave; u < (nrb - full) * RS_NG; u += 4)
     rs_rows_f32<1, 1>(A, rs_lds, Npad, full + u / RS_NG, u % RS_NG, C, n0, ncols, Dadd, g,
