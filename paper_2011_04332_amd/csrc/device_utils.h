@@ -111,17 +111,47 @@ __device__ __forceinline__ void block_sum_max(double (&v)[NS], double& mx, doubl
   }
 }
 
-__device__ __forceinline__ float block_max(float v, float* red) {
+// Float row shift (DPP row_shr:n), 0 where the source lies before the row.
+template <int N>
+__device__ __forceinline__ float dpp_row_shr_f(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 | N, 0xf, 0xf, false));
+}
+
+// Workgroup maxima of NV non-negative floats with a single barrier (DPP row
+// maxima, then the four row results of each wave, then the waves' results
+// through red, NV * (blockDim.x / 64) floats). The caller makes sure that no
+// thread still reads red from an earlier use. Every thread returns the
+// maxima. Call from uniform control flow.
+template <int NV>
+__device__ __forceinline__ void block_max_n(float (&v)[NV], float* red) {
   const int nw = blockDim.x / kWave;
   const int w = threadIdx.x / kWave;
   const int l = threadIdx.x % kWave;
-  v = wave_max(v);
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    float x = v[i];
+    x = fmaxf(x, dpp_row_shr_f<1>(x));
+    x = fmaxf(x, dpp_row_shr_f<2>(x));
+    x = fmaxf(x, dpp_row_shr_f<4>(x));
+    x = fmaxf(x, dpp_row_shr_f<8>(x));
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 15));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 31));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 47));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+    v[i] = fmaxf(fmaxf(r0, r1), fmaxf(r2, r3));
+  }
+  if (l == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[w * NV + i] = v[i];
+  }
   __syncthreads();
-  if (l == 0) red[w] = v;
-  __syncthreads();
-  float s = red[0];
-  for (int k = 1; k < nw; ++k) s = fmaxf(s, red[k]);
-  return s;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    float m = 0.f;
+    for (int k = 0; k < nw; ++k) m = fmaxf(m, red[k * NV + i]);
+    v[i] = m;
+  }
 }
 
 template <typename T>

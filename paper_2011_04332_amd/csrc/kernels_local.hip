@@ -382,12 +382,9 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
     }
   }
   if (a.colmax) {
-    float* redf = reinterpret_cast<float*>(red);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const float mx = block_max(cmax[d], redf);
-      if (tid == 0) a.colmax[a.cs.col0 + 3LL * lc + d] = mx;
-    }
+    // (red was last read in the volume projection, many barriers ago)
+    block_max_n<3>(cmax, reinterpret_cast<float*>(red));
+    if (tid < 3) a.colmax[a.cs.col0 + 3LL * lc + tid] = tid == 0 ? cmax[0] : tid == 1 ? cmax[1] : cmax[2];
   }
   if (want_energy) {
     double ev[1] = {e_acc};
