@@ -808,18 +808,24 @@ __global__ void __launch_bounds__(256) gemm_rs_lp_kernel(GemmArgs g) {
     const int rot = full > 0 ? (blockIdx.x / 8) % full : 0;
     auto phys = [&](int i) { return i + rot < full ? i + rot : i + rot - full; };
     vec_t a0[NKS], a1[NKS];
-    typename Rows::Epi e;
-    if (wave < full) Rows::load(A, Npad, phys(wave), lane, a0);
+    // the epilogue inputs (HBM) of a row block are requested one row block
+    // earlier than its operator image, two row blocks before their use
+    typename Rows::Epi e0, e1;
+    if (wave < full) {
+      Rows::load_epi(B, Dadd, Npad, phys(wave), 0, n0, ncols, add, lane, e0);
+      Rows::load(A, Npad, phys(wave), lane, a0);
+    }
+    if (wave + 4 < full) Rows::load_epi(B, Dadd, Npad, phys(wave + 4), 0, n0, ncols, add, lane, e1);
     for (int i = wave; i < full; i += 8) {
-      Rows::load_epi(B, Dadd, Npad, phys(i), 0, n0, ncols, add, lane, e);
       if (i + 4 < full) Rows::load(A, Npad, phys(i + 4), lane, a1);
       __builtin_amdgcn_sched_barrier(0);
-      Rows::run(a0, Bs, Npad, phys(i), 0, C, sc, n0, ncols, hm, beta, add, lane, e);
+      Rows::run(a0, Bs, Npad, phys(i), 0, C, sc, n0, ncols, hm, beta, add, lane, e0);
       if (i + 4 >= full) break;
-      Rows::load_epi(B, Dadd, Npad, phys(i + 4), 0, n0, ncols, add, lane, e);
+      if (i + 8 < full) Rows::load_epi(B, Dadd, Npad, phys(i + 8), 0, n0, ncols, add, lane, e0);
       if (i + 8 < full) Rows::load(A, Npad, phys(i + 8), lane, a0);
       __builtin_amdgcn_sched_barrier(0);
-      Rows::run(a1, Bs, Npad, phys(i + 4), 0, C, sc, n0, ncols, hm, beta, add, lane, e);
+      Rows::run(a1, Bs, Npad, phys(i + 4), 0, C, sc, n0, ncols, hm, beta, add, lane, e1);
+      if (i + 12 < full) Rows::load_epi(B, Dadd, Npad, phys(i + 12), 0, n0, ncols, add, lane, e1);
     }
   }
   // the remaining row blocks one column group at a time
