@@ -144,14 +144,20 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
   // ---- triangles: strain + area ----
   for (int base = 0; base < F; base += L.tch) {
     const int nt = min(L.tch, F - base);
-    // the next element's vertex ids are fetched one iteration ahead, so that
-    // their round trip overlaps the current element's work
-    int4 idn = tid < nt ? cv.tri_v[base + tid] : int4{0, 0, 0, 0};
+    // the next element's vertex ids and record are fetched one iteration
+    // ahead, so that their round trip overlaps the current element's work
+    const V4<T>* __restrict__ trec = reinterpret_cast<const V4<T>*>(cv.tri_rec);
+    const int t0 = base + min(tid, nt - 1);
+    int4 idn = cv.tri_v[t0];
+    V4<T> r0n = trec[2 * t0], r1n = trec[2 * t0 + 1];
     for (int t = base + tid; t < base + nt; t += BLOCK) {
       const int4 id = idn;
-      const V4<T> r0 = reinterpret_cast<const V4<T>*>(cv.tri_rec)[2 * t];
-      const V4<T> r1 = reinterpret_cast<const V4<T>*>(cv.tri_rec)[2 * t + 1];
-      if (t + BLOCK < base + nt) idn = cv.tri_v[t + BLOCK];
+      const V4<T> r0 = r0n, r1 = r1n;
+      if (t + BLOCK < base + nt) {
+        idn = cv.tri_v[t + BLOCK];
+        r0n = trec[2 * (t + BLOCK)];
+        r1n = trec[2 * (t + BLOCK) + 1];
+      }
       const T g00 = r0.x, g01 = r0.y, g10 = r0.z, g11 = r0.w, g20 = r1.x, g21 = r1.y;
       const T area = r1.z;
       const V4<T> qa = qs[id.x], qb = qs[id.y], qc = qs[id.z];
@@ -266,12 +272,18 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
   for (int base = 0; base < E; base += L.hch) {
     const int ne = min(L.hch, E - base);
     V4<T>* ys = reinterpret_cast<V4<T>*>(work);
-    int4 idn = tid < ne ? cv.hin_v[base + tid] : int4{0, 0, 0, 0};
+    const V4<T>* __restrict__ hrec = reinterpret_cast<const V4<T>*>(cv.hin_rec);
+    const int e0 = base + min(tid, ne - 1);
+    int4 idn = cv.hin_v[e0];
+    V4<T> r0n = hrec[2 * e0], r1n = hrec[2 * e0 + 1];
     for (int e = base + tid; e < base + ne; e += BLOCK) {
       const int4 id = idn;
-      const V4<T> r0 = reinterpret_cast<const V4<T>*>(cv.hin_rec)[2 * e];
-      const V4<T> r1 = reinterpret_cast<const V4<T>*>(cv.hin_rec)[2 * e + 1];
-      if (e + BLOCK < base + ne) idn = cv.hin_v[e + BLOCK];
+      const V4<T> r0 = r0n, r1 = r1n;
+      if (e + BLOCK < base + ne) {
+        idn = cv.hin_v[e + BLOCK];
+        r0n = hrec[2 * (e + BLOCK)];
+        r1n = hrec[2 * (e + BLOCK) + 1];
+      }
       const T k0 = r0.x, k1 = r0.y, k2 = r0.z, k3 = r0.w, ce = r1.x, rr = r1.y;
       const V4<T> qi = qs[id.x], qj = qs[id.y], qk = qs[id.z], ql = qs[id.w];
       T yq[3];
