@@ -659,14 +659,13 @@ struct RsLpRows {
     float4 c[NGU];
   };
   // register image of one row block: k-step ks of lane l covers
-  // k = 32 ks + 8 (l/16) .. + 7 of row 16 rb + l%16
-  static __device__ __forceinline__ void load(const L* __restrict__ A, int Npad, int rb, int lane,
+  // k = 32 ks + 8 (l/16) .. + 7 of row 16 rb + l%16, read from the fragment
+  // copy (one wave's k-step is 1 KB of consecutive memory)
+  static __device__ __forceinline__ void load(const L* __restrict__ Af, int Npad, int rb, int lane,
                                               vec_t (&dst)[NKS]) {
-    const L* __restrict__ arow = A + (size_t)(rb * 16 + (lane & 15)) * Npad;
-    const int kl = 8 * (lane >> 4);
+    const L* __restrict__ src = Af + ((size_t)rb * NKS * 64 + lane) * 8;
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks)
-      dst[ks] = *reinterpret_cast<const vec_t*>(arow + min(32 * ks + kl, Npad - 8));
+    for (int ks = 0; ks < NKS; ++ks) dst[ks] = *reinterpret_cast<const vec_t*>(src + 512 * ks);
   }
   // lane l holds rows 16 rb + 4 (l/16) .. + 3 of column group g0 + u, column
   // l%16 (clamped column index: columns past the last are never stored)
@@ -746,7 +745,7 @@ __global__ void __launch_bounds__(256) gemm_rs_lp_kernel(GemmArgs g) {
   typedef RsLpRows<L, NKS, 1> Rows1;
   typedef typename Mfma32<L>::vec_t vec_t;
   extern __shared__ float rs_lds_lp[];
-  const L* __restrict__ A = static_cast<const L*>(g.A);
+  const L* __restrict__ A = static_cast<const L*>(g.A_frag);
   const float* __restrict__ B = static_cast<const float*>(g.B);
   float* __restrict__ C = static_cast<float*>(g.C);
   const int Npad = g.Npad, ncols = g.ncols;
@@ -876,6 +875,7 @@ static hipError_t run_gemm_rs(int kind, const GemmArgs& g, hipStream_t st) {
   const size_t smem = rs_lds_bytes(kind, g.Npad);
   const void* fn = rs_kernel(kind, g.Npad);
   if (!fn || smem == 0 || smem > 160 * 1024) return hipErrorInvalidValue;
+  if (kind >= 2 && !g.A_frag) return hipErrorInvalidValue;
   GemmArgs a = g;
   void* args[] = {&a};
   const int blocks = (g.ncols + RS_NG * 16 - 1) / (RS_NG * 16);
@@ -945,6 +945,43 @@ hipError_t launch_gemm(int kind, int tile, const GemmArgs& g, hipStream_t st) {
     case kNumTilesTiled: return run_gemm_rs(kind, g, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ------------------------------------------------- 16-bit fragment order
+int gemm_rs_nks(int Npad) { return rs_nks(Npad) <= RS_KS_MAX ? rs_nks(Npad) : 0; }
+
+template <typename L>
+__global__ void __launch_bounds__(256) fragment_kernel(const L* __restrict__ op, int Npad, int nks,
+                                                       L* __restrict__ out) {
+  typedef typename Mfma32<L>::vec_t vec_t;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // one 8-value vector
+  const size_t total = (size_t)(Npad / 16) * nks * 64;
+  if (idx >= total) return;
+  const int lane = (int)(idx % 64);
+  const int ks = (int)((idx / 64) % nks);
+  const int rb = (int)(idx / (64 * (size_t)nks));
+  const int row = rb * 16 + (lane & 15), k0 = 32 * ks + 8 * (lane >> 4);
+  vec_t v;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = k0 + j < Npad ? op[(size_t)row * Npad + k0 + j] : L(0.0f);
+  *reinterpret_cast<vec_t*>(out + 8 * idx) = v;
+}
+
+hipError_t launch_convert_fragments(int kind, const void* op, int Npad, void* out,
+                                    hipStream_t st) {
+  const int nks = gemm_rs_nks(Npad);
+  if (Npad % 16 != 0 || nks == 0) return hipErrorInvalidValue;
+  const size_t total = (size_t)(Npad / 16) * nks * 64;
+  const dim3 grid((unsigned)((total + 255) / 256));
+  if (kind == 2)
+    hipLaunchKernelGGL(fragment_kernel<__bf16>, grid, dim3(256), 0, st,
+                       static_cast<const __bf16*>(op), Npad, nks, static_cast<__bf16*>(out));
+  else if (kind == 3)
+    hipLaunchKernelGGL(fragment_kernel<_Float16>, grid, dim3(256), 0, st,
+                       static_cast<const _Float16*>(op), Npad, nks, static_cast<_Float16*>(out));
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 }  // namespace npfem

@@ -77,6 +77,7 @@ struct ClassState {
   std::vector<void*> dev;      // device arrays of the class view
   void* view_ptrs[19] = {};    // device pointers (see upload_class)
   void* op = nullptr;          // stored global-step operator [Npad][Npad]
+  void* op_frag = nullptr;     // 16-bit operator in fragment order (column-stationary kernel)
   double beta = 0.0;           // split scale (low precision)
   double kappa = 0.0;          // max row sum of |Ainv - (h^2/m) I| / (h^2/m) (low precision)
   double r_rest = 0.0;         // max distance of a rest vertex from the rest centroid
@@ -212,6 +213,7 @@ struct npfem_batch_s {
     for (auto& c : cls) {
       for (void* p : c.dev) hipFree(p);
       if (c.op) hipFree(c.op);
+      if (c.op_frag) hipFree(c.op_frag);
     }
     for (void* p : allocs) hipFree(p);
     if (ckpt) hipFree(ckpt);
@@ -620,6 +622,11 @@ int factorise(npfem_batch_s* b, double dt) {
       }
     }
     e = launch_convert_operator(b->gemm_kind, dA, c.Npad, hm, c.beta, c.op, nullptr);
+    if (e == hipSuccess && b->gemm_kind >= 2 && gemm_rs_nks(c.Npad) > 0) {
+      if (!c.op_frag)
+        e = hipMalloc(&c.op_frag, esz * (size_t)(c.Npad / 16) * gemm_rs_nks(c.Npad) * 512);
+      if (e == hipSuccess) e = launch_convert_fragments(b->gemm_kind, c.op, c.Npad, c.op_frag, nullptr);
+    }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
       cleanup();
@@ -663,6 +670,7 @@ int enqueue_solve(npfem_batch_s* b, ClassState& c, T* B, T* C, const T* D, doubl
   const bool adapt = step_solve && sweeps_adaptive(b);
   GemmArgs g;
   g.A = c.op;
+  g.A_frag = c.op_frag;
   g.B = B + c.elem0;
   g.C = C + c.elem0;
   g.D = D ? D + c.elem0 : nullptr;
@@ -872,6 +880,7 @@ int autotune(npfem_batch_s* b, double h) {
     if (c.n_cells == 0) continue;
     GemmArgs g;
     g.A = c.op;
+    g.A_frag = c.op_frag;
     g.B = static_cast<T*>(b->rhs) + c.elem0;
     g.C = static_cast<T*>(b->delta) + c.elem0;
     // (the step's solve adds the previous iterate; the other iterate buffer

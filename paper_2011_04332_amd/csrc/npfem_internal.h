@@ -104,6 +104,9 @@ enum EpilogueMode : int { EPI_SET = 0, EPI_ADD = 1, EPI_SPLIT_SET = 2, EPI_SPLIT
 
 struct GemmArgs {
   const void* A;       // [Npad][Npad] symmetric operator (element type per kernel)
+  // 16-bit operator in fragment order for the column-stationary kernel
+  // (launch_convert_fragments), required by it, ignored by the others
+  const void* A_frag = nullptr;
   const void* B;       // input columns [ncols][Npad] (float or double)
   void* C;             // output columns [ncols][Npad]
   const void* D = nullptr;  // SET modes: columns added to the product (may be C), or nullptr
@@ -162,6 +165,15 @@ void gemm_tile_shape(int tile, int* bm, int* bn);
 hipError_t launch_spd_inverse(double* A, int n, int ld, double* scratch, int* pivot_fail,
                               hipStream_t st);
 // Convert an FP64 padded inverse to the stored operator.
+// Copies the 16-bit operator [Npad][Npad] (kind 2: BF16, 3: FP16) into
+// fragment order: for row block rb (16 rows), k-step ks (32 k) and lane l,
+// the 8 values of row 16 rb + l%16 at k = 32 ks + 8 (l/16) .. + 7 (zero past
+// Npad) are contiguous at ((rb * nks + ks) * 64 + l) * 8, so that a wave's
+// load of one k-step of a row block reads 1 KB of consecutive memory. out
+// holds (Npad / 16) * nks * 512 values, nks = gemm_rs_nks(Npad) (0 where
+// the column-stationary kernel does not take the class: then no copy).
+hipError_t launch_convert_fragments(int kind, const void* op, int Npad, void* out, hipStream_t st);
+int gemm_rs_nks(int Npad);
 hipError_t launch_convert_operator(int kind, const double* Ainv, int Npad, double hm, double beta,
                                    void* out, hipStream_t st);
 hipError_t launch_max_abs_split(const double* Ainv, int n, int Npad, double hm, double* out,
