@@ -226,8 +226,8 @@ def main():
     for _ in range(max(1, a.warmup)):
         b.step(f, dt, n_iter)
     b.sync_status()
-    configs = [b.config(k) for k in range(len(s.classes))]
-    print(f"[bench] launch configs per class (local block, tile m, tile n, sweeps): {configs}",
+    launch_cfgs = [b.config(k) for k in range(len(s.classes))]
+    print(f"[bench] launch configs per class (local block, tile m, tile n, sweeps): {launch_cfgs}",
           file=sys.stderr, flush=True)
     pos.copy_(x_init)
     vel.copy_(v_init)
@@ -253,7 +253,7 @@ def main():
         bt = solver.Batch(meshes, s.cell_class, pos, vel,
                           cell_weights=None if s.uniform_weights() else s.weights,
                           precision=a.precision, kernel_timing=True)
-        for k, cfg in enumerate(configs):
+        for k, cfg in enumerate(launch_cfgs):
             # pins the launch shapes; the sweep count stays automatic (with
             # 16-bit products, sweeps a cell does not need are skipped)
             bt.set_config(k, (cfg[0], cfg[1], cfg[2], -1))
@@ -267,7 +267,7 @@ def main():
         bt.close()
         traffic = measured_traffic(a.workload, a.precision)
         entries = {}
-        sweeps = configs[0][3]
+        sweeps = launch_cfgs[0][3]
         for kind in ("local", "global"):
             ms, n = kt[kind]
             avg_s = ms / n * 1e-3
@@ -401,7 +401,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: {desc}", "cells": s.n_cells, "pd_iterations": n_iter,
                    "launch": {s.classes[k].name: {"local_block": c[0], "gemm_tile": [c[1], c[2]],
-                                                  "sweeps": c[3]} for k, c in enumerate(configs)},
+                                                  "sweeps": c[3]} for k, c in enumerate(launch_cfgs)},
                    "dt": dt, "precision": a.precision},
         "roofline": roof,
         "cpu_baseline": cpu,

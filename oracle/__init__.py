@@ -21,8 +21,9 @@ What it computes, and where that comes from:
   per-cell volume.
 
 The paper prints no discretised formulas; every formula here is the published
-projective-dynamics method instantiated for these four potentials, with each
-reading listed in DESIGN.md under "Readings of the paper".
+projective-dynamics method instantiated for these four potentials; where the
+paper leaves a choice open, the function that makes it says which reading it
+takes.
 
 Modules: ``operators`` (rest-shape operators and the system matrix),
 ``projections`` (local step), ``solver`` (step / rollout / energy), ``newton``
