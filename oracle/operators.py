@@ -196,6 +196,9 @@ def laplacians(ops: CellOperators):
 
 
 def system_matrix(ops: CellOperators, weights, mass: float, dt: float) -> np.ndarray:
+    """A = (m/h^2 + w_v) I + (w_s + w_a) L_tri + w_b L_bend (lumped, uniform
+    vertex mass; the volume constraint's selection matrix is the identity,
+    unscaled: readings that match the right-hand side)."""
     ws, wa, wb, wv = (float(w) for w in weights)
     Lt, Lb = laplacians(ops)
     n = ops.n_verts

@@ -38,12 +38,17 @@ def thin_svd(F: np.ndarray):
 
 
 def project_strain(U, s, Vt):
+    """Strain target: the polar factor U V^T of F = U diag(s) V^T, the
+    nearest 3x2 matrix with orthonormal columns (reading: exact projection,
+    as in classic projective dynamics; the paper prints no formula)."""
     return U @ Vt
 
 
 def area_root(s1: np.ndarray, s2: np.ndarray) -> np.ndarray:
     """Positive real root t of t^4 - s1 t^3 + s2 t - 1 minimising
-    (t - s1)^2 + (1/t - s2)^2 (ties: smaller t).
+    (t - s1)^2 + (1/t - s2)^2 (ties: smaller t). Reading: the area target is
+    the nearest matrix with singular values (t, 1/t), i.e. with unit area
+    ratio; the quartic is the stationarity condition of that distance.
 
     Roots are the eigenvalues of the quartic's companion matrix (what
     ``numpy.roots`` computes), batched; each real root gets one Newton polish.
@@ -83,6 +88,7 @@ def area_root(s1: np.ndarray, s2: np.ndarray) -> np.ndarray:
 
 
 def project_area(U, s, Vt):
+    """Area target U diag(t, 1/t) V^T with t from area_root."""
     t = area_root(s[:, 0], s[:, 1])
     d = np.stack([t, 1.0 / t], axis=1)
     return U @ (d[:, :, None] * Vt)
@@ -94,6 +100,9 @@ def bending_vectors(q: np.ndarray, H: np.ndarray, K: np.ndarray) -> np.ndarray:
 
 
 def project_bending(y: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """Bending target: y rescaled to its rest magnitude r (reading: the
+    hinge keeps the rest length of its cotangent stencil vector; y itself
+    where |y| = 0, where every direction is equally near)."""
     n = np.linalg.norm(y, axis=1)
     out = y.copy()
     nz = n > 0.0
@@ -103,7 +112,12 @@ def project_bending(y: np.ndarray, r: np.ndarray) -> np.ndarray:
 
 def project_volume(q: np.ndarray, tris: np.ndarray, vol_rest: float, radius: float,
                    max_iter: int = 100, vol_tol: float = 1e-13, step_tol: float = 1e-15):
-    """Closest point to q on {V(p) = vol_rest}; returns (p, iterations used)."""
+    """Closest point to q on {V(p) = vol_rest}; returns (p, iterations used).
+
+    Reading: the volume constraint acts on the whole cell and its target is
+    the exact closest point (the KKT point p = q + lam grad V(p)), reached by
+    iterating that fixed-point map from p = q until the volume matches to
+    vol_tol and the iterate has settled to step_tol of the cell radius."""
     p = q.copy()
     for it in range(1, max_iter + 1):
         g = ops_mod.volume_gradient(p, tris)

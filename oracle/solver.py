@@ -39,6 +39,9 @@ class Params:
 
 
 def rhs(o: ops_mod.CellOperators, P: dict, s: np.ndarray, prm: Params) -> np.ndarray:
+    """Right-hand side (m/h^2) s + sum of the constraints' weighted targets.
+    Reading of the weights: strain and area scaled by the rest triangle area,
+    bending by c_e = 3 / (A1 + A2), volume per vertex unscaled."""
     ws, wa, wb, wv = prm.weights
     b = (prm.mass / prm.dt ** 2) * s
     # triangles: rows of A_t G_t (w_s Ps^T + w_a Pa^T) go to the triangle's vertices
