@@ -79,7 +79,9 @@ class CellSolver:
 
     def step(self, x, v, f, n_iter, record_energy=False):
         """One time step; returns (x_new, v_new, energies) with energies
-        E(q^0..q^n_iter) when requested."""
+        E(q^0..q^n_iter) when requested. Readings: a fixed count of n_iter
+        local/global iterations from q^0 = s (the inertial prediction),
+        v = (q - x) / h, no damping."""
         h, m = self.prm.dt, self.prm.mass
         s = x + h * v + (h * h / m) * f
         q = s.copy()
