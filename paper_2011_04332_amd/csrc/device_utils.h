@@ -85,8 +85,12 @@ __device__ __forceinline__ double wave_max_dpp(double v) {
 // that a call never overwrites the half that the previous call is still
 // reading. Identical totals in every thread. Call from uniform control flow.
 // The max input must be >= 0 (lanes with no data contribute 0).
+// block_sum_max in two halves around a barrier the caller provides: the
+// waves' partials are written by block_sum_max_write and combined, after any
+// barrier, by block_sum_max_read (same arithmetic, same totals).
 template <int NS, bool WITH_MAX>
-__device__ __forceinline__ void block_sum_max(double (&v)[NS], double& mx, double* red, int buf) {
+__device__ __forceinline__ void block_sum_max_write(double (&v)[NS], double& mx, double* red,
+                                                    int buf) {
   constexpr int NV = NS + (WITH_MAX ? 1 : 0);
   const int nw = blockDim.x / kWave;
   const int w = threadIdx.x / kWave;
@@ -100,7 +104,14 @@ __device__ __forceinline__ void block_sum_max(double (&v)[NS], double& mx, doubl
     for (int i = 0; i < NS; ++i) r[w * NV + i] = v[i];
     if (WITH_MAX) r[w * NV + NS] = mx;
   }
-  __syncthreads();
+}
+
+template <int NS, bool WITH_MAX>
+__device__ __forceinline__ void block_sum_max_read(double (&v)[NS], double& mx, const double* red,
+                                                   int buf) {
+  constexpr int NV = NS + (WITH_MAX ? 1 : 0);
+  const int nw = blockDim.x / kWave;
+  const double* r = red + (size_t)buf * (NS + 1) * nw;
 #pragma unroll
   for (int i = 0; i < NS; ++i) v[i] = 0.0;
   if (WITH_MAX) mx = 0.0;
@@ -109,6 +120,13 @@ __device__ __forceinline__ void block_sum_max(double (&v)[NS], double& mx, doubl
     for (int i = 0; i < NS; ++i) v[i] += r[k * NV + i];
     if (WITH_MAX) mx = fmax(mx, r[k * NV + NS]);
   }
+}
+
+template <int NS, bool WITH_MAX>
+__device__ __forceinline__ void block_sum_max(double (&v)[NS], double& mx, double* red, int buf) {
+  block_sum_max_write<NS, WITH_MAX>(v, mx, red, buf);
+  __syncthreads();
+  block_sum_max_read<NS, WITH_MAX>(v, mx, red, buf);
 }
 
 // Float row shift (DPP row_shr:n), 0 where the source lies before the row.

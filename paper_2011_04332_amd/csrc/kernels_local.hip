@@ -115,31 +115,17 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
 #pragma unroll
   for (int j = 0; j < VPT; ++j) acc[j][0] = acc[j][1] = acc[j][2] = T(0);
 
-  // ---- volume: closest point of q on {V(p) = V_rest} (local_common.h) ----
-  // (ps is scratch inside the projection; no thread reads it after the
-  // projection's last barrier, so the triangle chunks may overwrite it)
-  {
-    V4<T>* ps = reinterpret_cast<V4<T>*>(work);
-    T g[VPT][3], p[VPT][3];
-    const double lam = volume_project<T, BLOCK, VPT, false, KT>(
-        cv, qs, ps, red, g, p, a.max_vol_iter, a.vol_tol, a.vol_abs, bad, ring);
-    // w_v (Pv - q) with Pv - q = lam g
-    const T wl = wv * T(lam);
-#pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-      const int v = tid + j * BLOCK;
-      if (v < N) {
-        acc[j][0] += wl * g[j][0];
-        acc[j][1] += wl * g[j][1];
-        acc[j][2] += wl * g[j][2];
-        if (want_energy) {
-          const double g2 = (double)g[j][0] * g[j][0] + (double)g[j][1] * g[j][1] +
-                            (double)g[j][2] * g[j][2];
-          e_acc += 0.5 * (double)wv * lam * lam * g2;
-        }
-      }
-    }
-  }
+  // ---- volume, first pass: closest point of q on {V(p) = V_rest}
+  // (local_common.h). The gradient at q and the waves' partial sums are
+  // formed here; the cell totals are read after the triangle phase's first
+  // barrier, which so serves the volume reduction too, and any further
+  // passes run after the triangle phase (they need the work region). ----
+  T g[VPT][3];
+  double vs[3], vmq;
+  volume_pass_local<T, BLOCK, VPT, KT>(cv, qs, qs, true, g, vs, vmq, ring);
+  block_sum_max_write<3, true>(vs, vmq, red, 0);
+  bool vol_pending = true, vol_conv = false;
+  double lam = 0.0;
 
   // ---- triangles: strain + area ----
   for (int base = 0; base < F; base += L.tch) {
@@ -197,6 +183,11 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
       }
     }
     __syncthreads();
+    if (vol_pending) {  // (uniform)
+      block_sum_max_read<3, true>(vs, vmq, red, 0);
+      lam = volume_lambda<T>(cv, vs, vmq, 0, 0.0, a.vol_tol, a.vol_abs, bad, vol_conv);
+      vol_pending = false;
+    }
     const bool whole = (nt == F);  // one chunk: every entry is in range
     // two fused multiply-adds per component
     auto tri_add = [&](int j, int t, V2<T> g2) {
@@ -254,6 +245,39 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
       }
     }
     __syncthreads();
+  }
+
+  if (vol_pending) {  // (a mesh without triangles: no chunk barrier ran)
+    __syncthreads();
+    block_sum_max_read<3, true>(vs, vmq, red, 0);
+    lam = volume_lambda<T>(cv, vs, vmq, 0, 0.0, a.vol_tol, a.vol_abs, bad, vol_conv);
+  }
+  // ---- volume, further passes (the triangle chunks are done with the work
+  // region), then w_v (Pv - q) with Pv - q = lam g ----
+  if (!vol_conv && a.max_vol_iter > 1) {  // (uniform)
+    int ring2[VPT][KT > 0 ? KT : 1];
+    if constexpr (KT > 0) ring_indices<T, BLOCK, VPT, KT>(cv, ring2);
+    T p[VPT][3];
+    lam = volume_continue<T, BLOCK, VPT, false, KT>(cv, qs, reinterpret_cast<V4<T>*>(work), red,
+                                                    g, p, lam, vol_conv, 1, a.max_vol_iter,
+                                                    a.vol_tol, a.vol_abs, bad, ring2);
+  }
+  {
+    const T wl = wv * T(lam);
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const int v = tid + j * BLOCK;
+      if (v < N) {
+        acc[j][0] += wl * g[j][0];
+        acc[j][1] += wl * g[j][1];
+        acc[j][2] += wl * g[j][2];
+        if (want_energy) {
+          const double g2 = (double)g[j][0] * g[j][0] + (double)g[j][1] * g[j][1] +
+                            (double)g[j][2] * g[j][2];
+          e_acc += 0.5 * (double)wv * lam * lam * g2;
+        }
+      }
+    }
   }
 
   // inertia term of the own vertices, cterm - (m/h^2) delta, loaded here so

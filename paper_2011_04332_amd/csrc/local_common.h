@@ -121,62 +121,81 @@ __device__ __forceinline__ void ring_indices(const ClassView<T>& cv, int (&ring)
   }
 }
 
-template <typename T, int BLOCK, int VPT, bool STORE_P, int KT = 0>
-__device__ double volume_project(const ClassView<T>& cv, const V4<T>* qs, V4<T>* ps, double* red,
-                                 T (&g)[VPT][3], T (&pv)[VPT][3], int max_it, double vol_tol,
-                                 double vol_abs, int& bad,
-                                 const int (&fan)[VPT][KT > 0 ? KT : 1]) {
+// One pass's per-thread part: the gradient g at src (q itself on the first
+// pass) for this thread's vertices and its partial sums s[0] = p.g,
+// s[1] = |g|^2, s[2] = g.(q - p) (later passes) and mq = max |q|^2 (first).
+template <typename T, int BLOCK, int VPT, int KT>
+__device__ __forceinline__ void volume_pass_local(const ClassView<T>& cv, const V4<T>* qs,
+                                                  const V4<T>* src, bool first,
+                                                  T (&g)[VPT][3], double (&s)[3], double& mq,
+                                                  const int (&fan)[VPT][KT > 0 ? KT : 1]) {
   const int N = cv.N, tid = threadIdx.x;
-  const V4<T>* src = qs;  // current iterate p
-  double lam = 0.0;
-  bool stored = false;
-  for (int it = 0; it < max_it; ++it) {
-    double s[3] = {0.0, 0.0, 0.0};
-    double mq = 0.0;
+  s[0] = s[1] = s[2] = 0.0;
+  mq = 0.0;
 #pragma unroll
-    for (int j = 0; j < VPT; ++j) {
-      const int v = tid + j * BLOCK;
-      g[j][0] = g[j][1] = g[j][2] = T(0);
-      if (v < N) {
-        T gx, gy, gz;
-        if constexpr (KT > 0) {
-          volume_gradient_ring<T, KT>(src, fan[j], gx, gy, gz);
-        } else {
-          volume_gradient<T, 0>(cv, src, v, gx, gy, gz);
-        }
-        g[j][0] = gx;
-        g[j][1] = gy;
-        g[j][2] = gz;
-        const V4<T> q = qs[v];
-        const V4<T> p = it == 0 ? q : src[v];
-        s[0] += (double)(p.x * gx + p.y * gy + p.z * gz);
-        s[1] += (double)(gx * gx + gy * gy + gz * gz);
-        if (it > 0) s[2] += (double)(gx * (q.x - p.x) + gy * (q.y - p.y) + gz * (q.z - p.z));
-        else mq = fmax(mq, (double)(q.x * q.x + q.y * q.y + q.z * q.z));
+  for (int j = 0; j < VPT; ++j) {
+    const int v = tid + j * BLOCK;
+    g[j][0] = g[j][1] = g[j][2] = T(0);
+    if (v < N) {
+      T gx, gy, gz;
+      if constexpr (KT > 0) {
+        volume_gradient_ring<T, KT>(src, fan[j], gx, gy, gz);
+      } else {
+        volume_gradient<T, 0>(cv, src, v, gx, gy, gz);
       }
+      g[j][0] = gx;
+      g[j][1] = gy;
+      g[j][2] = gz;
+      const V4<T> q = qs[v];
+      const V4<T> p = first ? q : src[v];
+      s[0] += (double)(p.x * gx + p.y * gy + p.z * gz);
+      s[1] += (double)(gx * gx + gy * gy + gz * gz);
+      if (!first) s[2] += (double)(gx * (q.x - p.x) + gy * (q.y - p.y) + gz * (q.z - p.z));
+      else mq = fmax(mq, (double)(q.x * q.x + q.y * q.y + q.z * q.z));
     }
-    // one barrier; afterwards every read of src in this iteration is done
-    if (it == 0) block_sum_max<3, true>(s, mq, red, 0);
-    else block_sum_max<3, false>(s, mq, red, it & 1);
-    double lam_new = (cv.vol_rest - s[0] / 3.0 - s[2]) / s[1];
-    if (!isfinite(lam_new)) {
-      bad = 1;
-      lam_new = 0.0;
-    }
-    const double gn = sqrt(s[1]);
-    const double allow = fmax(vol_tol * fabs(lam_new) * gn, vol_abs);
-    bool conv;
-    if (it == 0) {
-      const double hb = (double)cv.DT / 3.0 * sqrt(mq);
-      conv = 5.0 * lam_new * lam_new * hb * gn <= allow;
-    } else {
-      conv = fabs(lam_new - lam) * gn <= allow;
-    }
-    lam = lam_new;
-    const bool last = conv || it + 1 == max_it;
+  }
+}
+
+// The multiplier of pass it from the cell totals, and the stopping test
+// (see volume_project).
+template <typename T>
+__device__ __forceinline__ double volume_lambda(const ClassView<T>& cv, const double (&s)[3],
+                                                double mq, int it, double lam_prev,
+                                                double vol_tol, double vol_abs, int& bad,
+                                                bool& conv) {
+  double lam_new = (cv.vol_rest - s[0] / 3.0 - s[2]) / s[1];
+  if (!isfinite(lam_new)) {
+    bad = 1;
+    lam_new = 0.0;
+  }
+  const double gn = sqrt(s[1]);
+  const double allow = fmax(vol_tol * fabs(lam_new) * gn, vol_abs);
+  if (it == 0) {
+    const double hb = (double)cv.DT / 3.0 * sqrt(mq);
+    conv = 5.0 * lam_new * lam_new * hb * gn <= allow;
+  } else {
+    conv = fabs(lam_new - lam_prev) * gn <= allow;
+  }
+  return lam_new;
+}
+
+// Passes after the first `done` ones, whose last gave (lam, g, conv): publish
+// p = q + lam g, take the gradient there, and so on (see volume_project).
+// Uses red halves (pass & 1); ps needs N + 1 records. Call from uniform
+// control flow.
+template <typename T, int BLOCK, int VPT, bool STORE_P, int KT>
+__device__ double volume_continue(const ClassView<T>& cv, const V4<T>* qs, V4<T>* ps,
+                                  double* red, T (&g)[VPT][3], T (&pv)[VPT][3], double lam,
+                                  bool conv, int done, int max_it, double vol_tol,
+                                  double vol_abs, int& bad,
+                                  const int (&fan)[VPT][KT > 0 ? KT : 1]) {
+  const int N = cv.N, tid = threadIdx.x;
+  bool stored = false;
+  for (int it = done;; ++it) {
+    const bool last = conv || it >= max_it;
     if (last && !STORE_P) break;
-    // publish p for the next iteration's gradient (or for the caller)
-    const T lt = T(lam_new);
+    // publish p for the next pass's gradient (or for the caller)
+    const T lt = T(lam);
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
@@ -189,10 +208,28 @@ __device__ double volume_project(const ClassView<T>& cv, const V4<T>* qs, V4<T>*
     if (!stored && tid == 0) ps[N] = V4<T>{T(0), T(0), T(0), T(0)};
     stored = true;
     __syncthreads();
-    src = ps;
     if (last) break;
+    double s[3], mq;
+    volume_pass_local<T, BLOCK, VPT, KT>(cv, qs, ps, false, g, s, mq, fan);
+    // one barrier; afterwards every read of ps in this pass is done
+    block_sum_max<3, false>(s, mq, red, it & 1);
+    lam = volume_lambda<T>(cv, s, mq, it, lam, vol_tol, vol_abs, bad, conv);
   }
   return lam;
+}
+
+template <typename T, int BLOCK, int VPT, bool STORE_P, int KT = 0>
+__device__ double volume_project(const ClassView<T>& cv, const V4<T>* qs, V4<T>* ps, double* red,
+                                 T (&g)[VPT][3], T (&pv)[VPT][3], int max_it, double vol_tol,
+                                 double vol_abs, int& bad,
+                                 const int (&fan)[VPT][KT > 0 ? KT : 1]) {
+  double s[3], mq;
+  volume_pass_local<T, BLOCK, VPT, KT>(cv, qs, qs, true, g, s, mq, fan);
+  block_sum_max<3, true>(s, mq, red, 0);
+  bool conv;
+  const double lam = volume_lambda<T>(cv, s, mq, 0, 0.0, vol_tol, vol_abs, bad, conv);
+  return volume_continue<T, BLOCK, VPT, STORE_P, KT>(cv, qs, ps, red, g, pv, lam, conv, 1, max_it,
+                                                     vol_tol, vol_abs, bad, fan);
 }
 
 }  // namespace npfem
