@@ -105,9 +105,22 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
   int ring[VPT][KT > 0 ? KT : 1];
   if constexpr (KT > 0) ring_indices<T, BLOCK, VPT, KT>(cv, ring);
 
-  // ---- stage q = x + delta ----
-  for (int v = tid; v < N; v += BLOCK)
-    qs[v] = V4<T>{px[v] + dcol[v], py[v] + dcol[Npad + v], pz[v] + dcol[2 * Npad + v], T(0)};
+  // ---- stage q = x + delta (up to six vertex sets per thread: every set's
+  // loads in flight at once, VPT * BLOCK >= N, clamped reads) ----
+  if constexpr (VPT <= 6) {
+    V4<T> sq[VPT];
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const int v = min(tid + j * BLOCK, N - 1);
+      sq[j] = V4<T>{px[v] + dcol[v], py[v] + dcol[Npad + v], pz[v] + dcol[2 * Npad + v], T(0)};
+    }
+#pragma unroll
+    for (int j = 0; j < VPT; ++j)
+      if (tid + j * BLOCK < N) qs[tid + j * BLOCK] = sq[j];
+  } else {
+    for (int v = tid; v < N; v += BLOCK)
+      qs[v] = V4<T>{px[v] + dcol[v], py[v] + dcol[Npad + v], pz[v] + dcol[2 * Npad + v], T(0)};
+  }
   if (tid == 0) qs[N] = V4<T>{T(0), T(0), T(0), T(0)};
   __syncthreads();
 
