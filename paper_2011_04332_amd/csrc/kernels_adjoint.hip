@@ -89,12 +89,31 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
   int bad = 0;
   double wacc[4] = {0.0, 0.0, 0.0, 0.0};
 
-  for (int v = tid; v < N; v += BLOCK) {
+  // the records of vertex v: q = x + delta_0, delta_0 - delta_1, lambda
+  auto fetch = [&](int v, V4<T>& q, V4<T>& dd, V4<T>& l) {
     const T x0 = px[v], x1 = py[v], x2 = pz[v];
-    qs[v] = V4<T>{x0 + d0[v], x1 + d0[Npad + v], x2 + d0[2 * Npad + v], T(0)};
-    dds[v] = V4<T>{d0[v] - d1[v], d0[Npad + v] - d1[Npad + v], d0[2 * Npad + v] - d1[2 * Npad + v],
-                   T(0)};
-    ls[v] = V4<T>{lcol[v], lcol[Npad + v], lcol[2 * Npad + v], T(0)};
+    q = V4<T>{x0 + d0[v], x1 + d0[Npad + v], x2 + d0[2 * Npad + v], T(0)};
+    dd = V4<T>{d0[v] - d1[v], d0[Npad + v] - d1[Npad + v], d0[2 * Npad + v] - d1[2 * Npad + v],
+               T(0)};
+    l = V4<T>{lcol[v], lcol[Npad + v], lcol[2 * Npad + v], T(0)};
+  };
+  if constexpr (VPT <= 4) {
+    // every vertex set's loads in flight at once (VPT * BLOCK >= N, clamped
+    // reads)
+    V4<T> fq[VPT], fd[VPT], fl[VPT];
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) fetch(min(tid + j * BLOCK, N - 1), fq[j], fd[j], fl[j]);
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const int v = tid + j * BLOCK;
+      if (v < N) {
+        qs[v] = fq[j];
+        dds[v] = fd[j];
+        ls[v] = fl[j];
+      }
+    }
+  } else {
+    for (int v = tid; v < N; v += BLOCK) fetch(v, qs[v], dds[v], ls[v]);
   }
   if (tid == 0) ls[N] = V4<T>{T(0), T(0), T(0), T(0)};
   __syncthreads();
