@@ -425,20 +425,21 @@ __device__ __forceinline__ void rs_rows_f32(const float* __restrict__ A, const f
     for (int u = 0; u < NGU; ++u)
 #pragma unroll
       for (int j = 0; j < NJ; ++j) acc[r][u][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // operator in fragment order: the 4 values of lane l for row block rb and
+  // 16-k group kg at ((rb * nkg + kg) * 64 + l) * 4 (1 KB per wave load)
+  const int nkg = Npad / 16;
   const float* arow[NR];
 #pragma unroll
-  for (int r = 0; r < NR; ++r)
-    arow[r] = A + (size_t)((rb + r) * 16 + (lane & 15)) * Npad + 4 * (lane >> 4);
+  for (int r = 0; r < NR; ++r) arow[r] = A + ((size_t)(rb + r) * nkg * 64 + lane) * 4;
   // record (4 kg + lane/16, g * 16 + lane%16) for k-group kg
   const float* bcol[NGU];
 #pragma unroll
   for (int u = 0; u < NGU; ++u) bcol[u] = Bs + 4 * ((lane >> 4) * RS_BN + (g0 + u) * 16 + (lane & 15));
-  const int nkg = Npad / 16;
   // Straight-line prefetch: out-of-range prefetches re-read the last group
   // (clamped address, value unused), so the loop body has no branches and the
   // compiler can wait for exactly the load it needs.
   auto load_a = [&](int r, int kg) {
-    return *reinterpret_cast<const float4*>(arow[r] + 16 * min(kg, nkg - 1));
+    return *reinterpret_cast<const float4*>(arow[r] + 256 * min(kg, nkg - 1));
   };
   auto step = [&](int kg, const float4 (&a)[NR]) {
     float4 b[NGU];
@@ -551,7 +552,7 @@ __device__ __forceinline__ void rs_rows_f32(const float* __restrict__ A, const f
 
 __global__ void __launch_bounds__(256) gemm_rs_f32_kernel(GemmArgs g) {
   extern __shared__ float rs_lds[];
-  const float* __restrict__ A = static_cast<const float*>(g.A);
+  const float* __restrict__ A = static_cast<const float*>(g.A_frag);
   const float* __restrict__ B = static_cast<const float*>(g.B);
   float* __restrict__ C = static_cast<float*>(g.C);
   const int Npad = g.Npad, ncols = g.ncols;
@@ -875,7 +876,7 @@ static hipError_t run_gemm_rs(int kind, const GemmArgs& g, hipStream_t st) {
   const size_t smem = rs_lds_bytes(kind, g.Npad);
   const void* fn = rs_kernel(kind, g.Npad);
   if (!fn || smem == 0 || smem > 160 * 1024) return hipErrorInvalidValue;
-  if (kind >= 2 && !g.A_frag) return hipErrorInvalidValue;
+  if (kind != 1 && !g.A_frag) return hipErrorInvalidValue;
   GemmArgs a = g;
   void* args[] = {&a};
   const int blocks = (g.ncols + RS_NG * 16 - 1) / (RS_NG * 16);
@@ -950,6 +951,19 @@ hipError_t launch_gemm(int kind, int tile, const GemmArgs& g, hipStream_t st) {
 // ------------------------------------------------- 16-bit fragment order
 int gemm_rs_nks(int Npad) { return rs_nks(Npad) <= RS_KS_MAX ? rs_nks(Npad) : 0; }
 
+__global__ void __launch_bounds__(256) fragment_f32_kernel(const float* __restrict__ op, int Npad,
+                                                           float* __restrict__ out) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // one 4-value vector
+  const int nkg = Npad / 16;
+  const size_t total = (size_t)(Npad / 16) * nkg * 64;
+  if (idx >= total) return;
+  const int lane = (int)(idx % 64);
+  const int kg = (int)((idx / 64) % nkg);
+  const int rb = (int)(idx / (64 * (size_t)nkg));
+  const float* src = op + (size_t)(rb * 16 + (lane & 15)) * Npad + 16 * kg + 4 * (lane >> 4);
+  *reinterpret_cast<float4*>(out + 4 * idx) = *reinterpret_cast<const float4*>(src);
+}
+
 template <typename L>
 __global__ void __launch_bounds__(256) fragment_kernel(const L* __restrict__ op, int Npad, int nks,
                                                        L* __restrict__ out) {
@@ -969,6 +983,13 @@ __global__ void __launch_bounds__(256) fragment_kernel(const L* __restrict__ op,
 
 hipError_t launch_convert_fragments(int kind, const void* op, int Npad, void* out,
                                     hipStream_t st) {
+  if (kind == 0) {  // FP32: 16-k groups of 4 values per lane
+    if (Npad % 16 != 0) return hipErrorInvalidValue;
+    const size_t total = (size_t)(Npad / 16) * (Npad / 16) * 64;
+    hipLaunchKernelGGL(fragment_f32_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       st, static_cast<const float*>(op), Npad, static_cast<float*>(out));
+    return hipGetLastError();
+  }
   const int nks = gemm_rs_nks(Npad);
   if (Npad % 16 != 0 || nks == 0) return hipErrorInvalidValue;
   const size_t total = (size_t)(Npad / 16) * nks * 64;

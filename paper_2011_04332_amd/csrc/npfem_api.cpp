@@ -622,9 +622,14 @@ int factorise(npfem_batch_s* b, double dt) {
       }
     }
     e = launch_convert_operator(b->gemm_kind, dA, c.Npad, hm, c.beta, c.op, nullptr);
-    if (e == hipSuccess && b->gemm_kind >= 2 && gemm_rs_nks(c.Npad) > 0) {
-      if (!c.op_frag)
-        e = hipMalloc(&c.op_frag, esz * (size_t)(c.Npad / 16) * gemm_rs_nks(c.Npad) * 512);
+    // fragment copy for the column-stationary kernel, where it takes the
+    // class (FP32: 48 columns of Npad values in LDS; 16-bit: k-steps <= 24)
+    const bool frag = b->gemm_kind == 0 ? (size_t)48 * c.Npad * 4 <= 160 * 1024
+                    : b->gemm_kind >= 2 && gemm_rs_nks(c.Npad) > 0;
+    if (e == hipSuccess && frag) {
+      const size_t nfrag = b->gemm_kind == 0 ? (size_t)(c.Npad / 16) * (c.Npad / 16) * 256
+                                             : (size_t)(c.Npad / 16) * gemm_rs_nks(c.Npad) * 512;
+      if (!c.op_frag) e = hipMalloc(&c.op_frag, esz * nfrag);
       if (e == hipSuccess) e = launch_convert_fragments(b->gemm_kind, c.op, c.Npad, c.op_frag, nullptr);
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();

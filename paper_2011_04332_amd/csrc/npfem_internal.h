@@ -165,8 +165,11 @@ void gemm_tile_shape(int tile, int* bm, int* bn);
 hipError_t launch_spd_inverse(double* A, int n, int ld, double* scratch, int* pivot_fail,
                               hipStream_t st);
 // Convert an FP64 padded inverse to the stored operator.
-// Copies the 16-bit operator [Npad][Npad] (kind 2: BF16, 3: FP16) into
-// fragment order: for row block rb (16 rows), k-step ks (32 k) and lane l,
+// Copies the FP32 operator (kind 0) into fragment order: for row block rb
+// and 16-k group kg, lane l's 4 values of row 16 rb + l%16 at
+// k = 16 kg + 4 (l/16) .. + 3 at ((rb * (Npad/16) + kg) * 64 + l) * 4
+// ((Npad/16)^2 * 256 values). Copies the 16-bit operator (kind 2: BF16,
+// 3: FP16) likewise: for row block rb (16 rows), k-step ks (32 k) and lane l,
 // the 8 values of row 16 rb + l%16 at k = 32 ks + 8 (l/16) .. + 7 (zero past
 // Npad) are contiguous at ((rb * nks + ks) * 64 + l) * 8, so that a wave's
 // load of one k-step of a row block reads 1 KB of consecutive memory. out
