@@ -1,0 +1,184 @@
+"""Pins of the oracle's gradients (reverse mode and finite differences).
+
+* The differentiable projection forms equal the oracle's SVD projections.
+* One step with one PD iteration: q^0 = s does not depend on the weights, so
+  P_i(s) does not either and q^1 = A(w)^-1 b(w) with b = (m/h^2) s +
+  sum_i w_i S_i^T P_i(s) gives the exact closed form
+      dq^1/dw_i = A^-1 (S_i^T P_i(s) - (dA/dw_i) q^1),
+  dA/dw_s = dA/dw_a = L_tri, dA/dw_b = L_bend, dA/dw_v = I. Both the reverse
+  mode and the central differences must reproduce it (a mis-scaled step or a
+  dropped term of either fails here).
+* Free flight (all weights zero): x_T = x0 + T h v0 + h^2 T(T+1)/2 f/m, so
+  dL/df, dL/dx0 and dL/dv0 are known exactly.
+* Several steps and iterations on the stiff twin: reverse mode against
+  Richardson-extrapolated central differences.
+* The stored FP64 gradients of the differentiation workload
+  (golden/adjoint_reverse_rbc1024.json, written by make_adjoint_reverse.py)
+  agree with the stored central differences (golden/adjoint_fd_rbc1024.json)
+  within the differences' own uncertainty, and one stored cell is recomputed.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from npfem_workload import meshes, suspensions as W
+from oracle import gradients as Gr
+from oracle import operators as ops_mod
+from oracle import projections as proj
+from oracle import reverse as R
+from oracle import solver as S
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _cell(stiff=True, n_steps=2, n_iter=3):
+    s = W.adjoint_rbcs(n_cells=2, n_steps=n_steps, n_iter=n_iter)
+    if stiff:
+        s = W.stiff(s)
+    mc, x0, v0, f, w = s.cell_arrays(0)
+    tgt = s.extra["target"][:, s.cell_slice(0)].T
+    return s, mc, x0, v0, f, w, tgt
+
+
+def test_projection_forms_equal_svd_projections():
+    s, mc, x0, *_ = _cell()
+    o = S.operators_for(mc)
+    rng = np.random.default_rng(3)
+    for q in (x0, x0 + 0.05 * rng.standard_normal(x0.shape), 1.3 * x0):
+        F = ops_mod.deformation_gradients(q, o.tris, o.G)
+        U, sv, Vt = proj.thin_svd(F)
+        Ft = R._t(F)
+        assert np.abs(R.strain_targets(Ft).numpy() - proj.project_strain(U, sv, Vt)).max() < 1e-13
+        assert np.abs(R.area_targets(Ft).numpy() - proj.project_area(U, sv, Vt)).max() < 1e-13
+    # equal singular values (a rotation times a multiple of the identity)
+    th = 0.3
+    Q = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)], [0.0, 0.0]])
+    for scale in (0.5, 1.0, 1.7):
+        F = (scale * Q)[None]
+        U, sv, Vt = proj.thin_svd(F)
+        assert np.abs(R.area_targets(R._t(F)).numpy() - proj.project_area(U, sv, Vt)).max() < 1e-14
+
+
+def test_step_matches_oracle_step():
+    s, mc, x0, v0, f, w, _ = _cell()
+    o = S.operators_for(mc)
+    xa, va, _ = S.CellSolver(o, S.Params(tuple(w), mc.mass, s.dt)).step(x0, v0, f, 3)
+    xt, vt = R.step(R.TorchCell(o), R._t(x0), R._t(v0), R._t(f), R._t(w), mc.mass, s.dt, 3)
+    assert np.abs(xt.numpy() - xa).max() <= 1e-13 * np.abs(xa).max()
+
+
+def _closed_form_one_iteration(o, w, m, h, x0, v0, f, tgt):
+    """dL/dw_i for one step of one iteration, from the closed form."""
+    sv = x0 + h * v0 + (h * h / m) * f
+    P = proj.local_step(sv, o)
+    prm = S.Params(tuple(w), m, h)
+    A = ops_mod.system_matrix(o, w, m, h)
+    q = np.linalg.solve(A, S.rhs(o, P, sv, prm))
+    Lt, Lb = ops_mod.laplacians(o)
+    zero = np.zeros_like(sv)
+    out = []
+    for unit, dA in (((1, 0, 0, 0), Lt), ((0, 1, 0, 0), Lt), ((0, 0, 1, 0), Lb),
+                     ((0, 0, 0, 1), np.eye(len(sv)))):
+        StP = S.rhs(o, P, zero, S.Params(unit, m, h))  # S_i^T P_i(s)
+        dq = np.linalg.solve(A, StP - dA @ q)
+        out.append(float(np.sum(2.0 * (q - tgt) * dq)))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("stiff", [True, False])
+def test_one_iteration_closed_form(stiff):
+    s, mc, x0, v0, f, w, tgt = _cell(stiff)
+    o = S.operators_for(mc)
+    x0 = x0 + 0.02 * np.random.default_rng(5).standard_normal(x0.shape)  # away from rest
+    closed = _closed_form_one_iteration(o, w, mc.mass, s.dt, x0, v0, f, tgt)
+    _, gw, *_ = R.rollout_grad(o, w, mc.mass, s.dt, x0, v0, f, tgt, 1, 1)
+    assert np.all(np.abs(gw - closed) <= 1e-9 * np.abs(closed)), (gw, closed)
+    args = (mc, w, mc.mass, s.dt, x0, v0, f, tgt, 1, 1)
+    if stiff:
+        # central differences at relative steps h and h/2, Richardson-extrapolated
+        d1 = Gr.fd_weight_grad(*args, h=1e-3)
+        d2 = Gr.fd_weight_grad(*args, h=5e-4)
+        assert np.all(np.abs(d1 - closed) <= 1e-6 * np.abs(closed)), (d1, closed)
+        rich = (4.0 * d2 - d1) / 3.0
+        assert np.all(np.abs(rich - closed) <= 1e-7 * np.abs(closed)), (rich, closed)
+    else:
+        # at dt 1e-4 the weights move q by ~1e-4 of its size, and the quotient
+        # carries rounding noise eps L / (h w): a larger step, a looser bound
+        d = Gr.fd_weight_grad(*args, h=4e-3)
+        assert np.all(np.abs(d - closed) <= 1e-4 * np.abs(closed)), (d, closed)
+
+
+def test_free_flight_closed_form():
+    x, tri = meshes.rbc_mesh(2)
+    o = ops_mod.build_operators(x, tri)
+    rng = np.random.default_rng(0)
+    x0 = x.copy()
+    v0 = 0.1 * rng.standard_normal(x.shape)
+    f = 0.05 * rng.standard_normal(x.shape)
+    tgt = 1.01 * x0
+    T, h, m = 4, 1e-2, 1e-3
+    L, gw, gf, gx, gv = R.rollout_grad(o, (0, 0, 0, 0), m, h, x0, v0, f, tgt, 3, T)
+    xT = x0 + T * h * v0 + h * h * T * (T + 1) / 2.0 * f / m
+    g = 2.0 * (xT - tgt)
+    assert abs(L - np.sum((xT - tgt) ** 2)) <= 1e-12 * L
+    assert np.allclose(gf, g * h * h * T * (T + 1) / (2.0 * m), rtol=1e-11, atol=1e-14)
+    assert np.allclose(gx, g, rtol=1e-11, atol=1e-14)
+    assert np.allclose(gv, T * h * g, rtol=1e-11, atol=1e-14)
+
+
+def test_reverse_matches_differences_stiff():
+    """3 steps x 3 iterations on the stiff twin: weights and forces against
+    Richardson-extrapolated central differences."""
+    s, mc, x0, v0, f, w, tgt = _cell(True, n_steps=3, n_iter=3)
+    o = S.operators_for(mc)
+    _, gw, gf, gx, _ = R.rollout_grad(o, w, mc.mass, s.dt, x0, v0, f, tgt, 3, 3)
+    args = (mc, w, mc.mass, s.dt, x0, v0, f, tgt, 3, 3)
+    rich = (4.0 * Gr.fd_weight_grad(*args, h=5e-4) - Gr.fd_weight_grad(*args, h=1e-3)) / 3.0
+    assert np.all(np.abs(gw - rich) <= 1e-6 * np.abs(rich)), (gw, rich)
+    comps = [(3, 0), (200, 1), (611, 2)]
+    df1 = Gr.fd_force_grad(*args, comps, h=1e-4)
+    df2 = Gr.fd_force_grad(*args, comps, h=5e-5)
+    richf = (4.0 * df2 - df1) / 3.0
+    got = np.array([gf[v, d] for v, d in comps])
+    assert np.all(np.abs(got - richf) <= 1e-6 * np.abs(richf)), (got, richf)
+
+
+def _load(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return json.load(fh)
+
+
+def test_stored_reverse_gradients_match_stored_differences():
+    """FP64 reverse mode vs the central-difference fit, on the 8 cells of the
+    differentiation workload: within 1e-5 relative plus three times the fit's
+    largest residual. At dt 1e-4 the weights move the final positions by
+    ~1e-4 of their size, so the difference quotients carry rounding noise of
+    the 500-iteration rollout (that is why they are fitted over large steps);
+    the largest residual of a 4-point, 2-parameter fit understates the error
+    of its intercept (observed up to 1.6x here). The exact pins of the
+    reverse mode are the closed form and the stiff-twin differences above."""
+    rev = {r["cell"]: r for r in _load("adjoint_reverse_rbc1024.json")["cells"]}
+    fd = _load("adjoint_fd_rbc1024.json")["cells"]
+    assert len(fd) == 8 and set(rev) == {r["cell"] for r in fd}
+    for row in fd:
+        r = rev[row["cell"]]
+        g, d, unc = np.array(r["dw"]), np.array(row["dw"]), np.array(row["dw_fit_resid"])
+        assert np.all(np.abs(g - d) <= 1e-5 * np.abs(d) + 3.0 * unc), (row["cell"], g, d)
+        df = np.array(row["df"])
+        got = np.array([r["df_at"][f"{v},{k}"] for v, k in row["force_comps"]])
+        assert np.all(np.abs(got - df) <= 1e-5 * np.abs(df) + 1e-9), (row["cell"], got, df)
+
+
+@pytest.mark.slow
+def test_stored_reverse_gradient_recomputes():
+    """One stored cell recomputed from the oracle (50 steps x 10 iterations)."""
+    import sys
+    sys.path.insert(0, GOLDEN)
+    import make_adjoint_reverse as M
+    doc = _load("adjoint_reverse_rbc1024.json")
+    row = doc["cells"][0]
+    new = M.one_cell(row["cell"])
+    assert np.allclose(new["dw"], row["dw"], rtol=1e-12, atol=0)
+    assert np.allclose(new["df_sample"], row["df_sample"], rtol=1e-12, atol=0)
