@@ -18,16 +18,23 @@ class Rollout(torch.autograd.Function):
         with torch.no_grad():
             batch.pos.copy_(x0)
             batch.vel.copy_(v0)
-        f = forces.detach().contiguous()
+        # a private copy: the library records the forces buffer's address for
+        # the backward pass, so later in-place changes of the caller's tensor
+        # must not reach it
+        f = forces.detach().clone().contiguous()
         batch.rollout(f, dt, n_iter, n_steps, ckpt_every)
         ctx.batch = batch
-        ctx.keep = f  # the rollout recorded this buffer's address
+        ctx.keep = f
+        ctx.generation = batch.rollout_generation
         ctx.wdev = weights.device
         return batch.pos.clone(), batch.vel.clone()
 
     @staticmethod
     def backward(ctx, gx, gv):
         b = ctx.batch
+        if b.rollout_generation != ctx.generation:
+            raise RuntimeError("the batch ran another rollout after this one: its checkpoints "
+                               "are gone (one Rollout.apply per batch between backward passes)")
         gx = torch.zeros_like(b.pos) if gx is None else gx.contiguous()
         gv = None if gv is None else gv.contiguous()
         dw, df, dx0, dv0 = b.rollout_adjoint(gx, gv)

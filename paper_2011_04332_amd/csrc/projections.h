@@ -10,9 +10,15 @@
 // mu (d1 d2 - 1) gives d1 = (s1 + mu s2)/(1 - mu^2), d2 = (s2 + mu s1)/(1 - mu^2),
 // so with the same singular vectors
 //   Pa = F M,  M = (I + (mu/J) adj S) / (1 - mu^2),
-// where mu is the root near 0 of g(mu) = (1 - mu^2)^2 - J (1 + mu^2) - mu I1
-// (the constraint d1 d2 = 1). Neither form needs the singular vectors, and
-// both are smooth where s1 = s2.
+// where mu is a root of g(mu) = (1 - mu^2)^2 - J (1 + mu^2) - mu I1 (the
+// constraint d1 d2 = 1). Neither form needs the singular vectors, and both are
+// smooth where s1 = s2.
+// Which root: with s1 >= s2, the nearest point is d = (t, 1/t) with t the
+// largest positive root of t^4 - s1 t^3 + s2 t - 1 (its multiplier is
+// mu = t (t - s1)), and that mu is the only root of g in (-1, 1): g(-1) =
+// (s1 - s2)^2 >= 0, g(1) = -(I1 + 2J) < 0, and on (-1, -s2/s1] the product
+// (s1 + mu s2)(s2 + mu s1) is <= 0, so g > 0 there; the other roots of g lie
+// outside [-1, 1] and give a farther stationary point (or a negative d).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,6 +35,60 @@ __device__ __forceinline__ double f_rcp(double x) { return 1.0 / x; }
 // the correctly rounded square root and division.
 __device__ __forceinline__ float f_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double f_rsq(double x) { return 1.0 / sqrt(x); }
+
+// g(mu) and g'(mu) of the area multiplier's equation.
+template <typename T>
+__device__ __forceinline__ void area_g(T mu, T J, T I1, T& g, T& dg) {
+  const T u = T(1) - mu * mu;
+  g = u * u - J * (T(1) + mu * mu) - mu * I1;
+  dg = T(-4) * mu * u - T(2) * J * mu - I1;
+}
+
+// The area multiplier: the root of g in (-1, 1) (see the header).
+// Fast path: NEWTON unconditional steps from the linearisation (1 - J)/I1,
+// exact to first order in the strain (errors go ~e^2 -> e^4 -> e^8), accepted
+// when the last step is below the tolerance and the iterate lies in (-1, 1),
+// which then makes it the wanted root. Otherwise (strong compression or
+// stretch): Newton safeguarded by bisection on the bracket [-1, 1], where g
+// changes sign once. The tolerance is relative (2^-12 FP32, 2^-26 FP64: the
+// error after such a step is of the order of its square) plus an absolute
+// floor at the rounding noise of g near rest (J ~ 1 cancels 1 - mu^2).
+// Sets bad when the safeguarded iteration does not settle.
+template <typename T, int NEWTON>
+__device__ __forceinline__ T area_multiplier(T J, T I1, int& bad) {
+  constexpr T rtol = sizeof(T) == 4 ? T(1.0 / 4096.0) : T(1.0 / 67108864.0);
+  constexpr T atol = sizeof(T) == 4 ? T(4.76837158203125e-7) : T(8.881784197001252e-16);
+  T mu = (T(1) - J) * f_rcp(I1);
+  T g, dg, step = T(0);
+#pragma unroll
+  for (int it = 0; it < NEWTON; ++it) {
+    area_g(mu, J, I1, g, dg);
+    step = g * f_rcp(dg);
+    mu -= step;
+  }
+  if (fabs(step) <= rtol * fabs(mu) + atol && fabs(mu) < T(1)) return mu;
+  T lo = T(-1), hi = T(1);
+  mu = T(0);
+  for (int it = 0; it < 96; ++it) {
+    area_g(mu, J, I1, g, dg);
+    if (g > T(0)) {
+      lo = mu;
+    } else if (g < T(0)) {
+      hi = mu;
+    } else {
+      return mu;  // exact root (or NaN input, flagged by the caller's tests)
+    }
+    step = g * f_rcp(dg);
+    T next = mu - step;
+    const T tol = rtol * fabs(mu) + atol;
+    if (fabs(step) <= tol) return (next >= lo && next <= hi) ? next : mu;
+    if (!(next > lo && next < hi)) next = T(0.5) * (lo + hi);
+    mu = next;
+    if (hi - lo <= tol) return mu;
+  }
+  bad = 1;
+  return mu;
+}
 
 template <typename T>
 struct TriProj;
@@ -47,8 +107,6 @@ struct TriProj {
   T pa[3][2];       // area projection F M
 };
 
-// Newton steps for mu from the linearisation (1 - J)/I1 (exact to first
-// order in the strain): errors go ~e^2 -> e^4 -> e^8 ...
 // TARGETS: also form P.ps and P.pa (the forward step applies W and M through
 // triangle_force instead). FP32 takes J and 1/J from one reciprocal square
 // root of |f0 x f1|^2, and 1/tau likewise; FP64 keeps square roots and
@@ -85,14 +143,7 @@ __device__ __forceinline__ void project_triangle(const T (&f)[3][2], TriProj<T>&
   P.w00 = (P.I1 + P.J - P.a) * iw;  // ((I1 + J) I - S) / (J tau)
   P.w01 = -P.b * iw;
   P.w11 = (P.I1 + P.J - P.c) * iw;
-  T mu = (T(1) - P.J) * f_rcp(P.I1);
-#pragma unroll
-  for (int it = 0; it < NEWTON; ++it) {
-    const T u = T(1) - mu * mu;
-    const T g = u * u - P.J * (T(1) + mu * mu) - mu * P.I1;
-    const T dg = T(-4) * mu * u - T(2) * P.J * mu - P.I1;
-    mu -= g * f_rcp(dg);
-  }
+  const T mu = area_multiplier<T, NEWTON>(P.J, P.I1, bad);
   P.mu = mu;
   P.om = f_rcp(T(1) - mu * mu);
   if (!isfinite(P.om)) bad = 1;

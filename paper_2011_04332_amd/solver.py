@@ -124,6 +124,7 @@ class Batch:
         self.precision = code
         self.dtype = dt_
         self._forces = None
+        self.rollout_generation = 0  # counts rollouts (the library keeps the last one's record)
 
     def step(self, forces: torch.Tensor, dt: float, n_iter: int):
         if not (forces.is_cuda and forces.dtype == self.dtype and forces.is_contiguous()
@@ -146,6 +147,7 @@ class Batch:
         """n_steps steps under constant forces, checkpointing every ckpt_every steps."""
         self._check_field(forces, "forces")
         self._forces = forces
+        self.rollout_generation += 1
         _lib.check(_lib.load().npfem_rollout(self.handle, forces.data_ptr(), float(dt), int(n_iter),
                                              int(n_steps), int(ckpt_every)))
 
