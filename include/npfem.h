@@ -212,6 +212,18 @@ int npfem_get_energy(npfem_batch b, double* host_out, int32_t capacity, int32_t*
  * positions into host [n_cells]. */
 int npfem_get_volume(npfem_batch b, double* host_out);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): npfem_get_volume
+ * with the per-cell staging buffer in a static device array of 65536
+ * doubles (one copy per device, held until the process ends) instead of the
+ * batch's own buffer. Allocates nothing. Writes the FP64 enclosed volume of
+ * every cell's current positions into host [n_cells]; synchronises the batch
+ * stream. Every call on one device shares that array: calls that overlap on
+ * one device (other host threads, other batches' streams) race and must be
+ * serialised by the caller. Errors: INVALID_ARG (NULL output, or more than
+ * 65536 cells), HIP. */
+int npfem_get_volume_noalloc(npfem_batch b, double* host_out);
+
 /* Launch configuration chosen for mesh class cls (after the first step, which
  * runs the autotuner when NPFEM_OPT_AUTOTUNE is set): out[0] local-step
  * workgroup size, out[1] / out[2] global-step GEMM tile rows / columns

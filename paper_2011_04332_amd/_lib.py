@@ -44,6 +44,7 @@ EXPORTED = [
     "npfem_sync_status",
     "npfem_get_energy",
     "npfem_get_volume",
+    "npfem_get_volume_noalloc",
     "npfem_batch_config",
     "npfem_set_batch_config",
     "npfem_kernel_times",
@@ -103,6 +104,7 @@ def load() -> ctypes.CDLL:
     lib.npfem_sync_status.argtypes = [P]
     lib.npfem_get_energy.argtypes = [P, P, I32, P]
     lib.npfem_get_volume.argtypes = [P, P]
+    lib.npfem_get_volume_noalloc.argtypes = [P, P]
     lib.npfem_kernel_times.argtypes = [P, P, P, I32]
     lib.npfem_batch_config.argtypes = [P, I32, P]
     lib.npfem_set_batch_config.argtypes = [P, I32, P]

@@ -5,6 +5,7 @@
 // hold one column per (cell, coordinate) of Npad entries (rows >= N are zero),
 // so that the global step is a plain GEMM over 3 * cells columns.
 #include <algorithm>
+#include <mutex>
 
 #include "device_utils.h"
 #include "npfem_internal.h"
@@ -299,6 +300,30 @@ hipError_t launch_residual(const ClassSlice<T>& cs, const T* rhs, const T* delta
   if (residual_smem<T, 2>(N) <= cap) return go(residual_kernel<T, 2>, 2, residual_smem<T, 2>(N));
   if (residual_smem<T, 1>(N) <= cap) return go(residual_kernel<T, 1>, 1, residual_smem<T, 1>(N));
   return hipErrorInvalidValue;
+}
+
+// Staging buffer of npfem_get_volume_noalloc (one double per cell), for callers
+// that cannot allocate device memory. Every device holds its own copy until
+// the process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (volume_scratch below).
+static __device__ __align__(256) double scratch[kVolumeScratchCells];
+
+hipError_t volume_scratch(double** out) {
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<double*>(p);
+  }
+  *out = addr[dev];
+  return hipSuccess;
 }
 
 template <typename T>

@@ -1382,6 +1382,29 @@ int npfem_get_volume(npfem_batch b, double* host_out) {
   return NPFEM_OK;
 }
 
+int npfem_get_volume_noalloc(npfem_batch b, double* host_out) {
+  if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
+  if (!host_out) return fail(NPFEM_ERR_INVALID_ARG, "host_out is NULL");
+  if (b->n_cells > kVolumeScratchCells)
+    return fail(NPFEM_ERR_INVALID_ARG,
+                "more cells than the static staging buffer of npfem_get_volume_noalloc holds (65536)");
+  DeviceGuard guard(b->device);
+  double* stage = nullptr;
+  HIP_TRY(volume_scratch(&stage), "staging buffer address");
+  for (auto& c : b->cls) {
+    hipError_t e = b->fp64 ? launch_volume<double>(slice_of<double>(c), (const double*)b->pos,
+                                                   b->sumN, stage, b->stream)
+                           : launch_volume<float>(slice_of<float>(c), (const float*)b->pos,
+                                                  b->sumN, stage, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "volume");
+  }
+  HIP_TRY(hipMemcpyAsync(host_out, stage, sizeof(double) * b->n_cells, hipMemcpyDeviceToHost,
+                         b->stream),
+          "volume read");
+  HIP_TRY(hipStreamSynchronize(b->stream), "sync");
+  return NPFEM_OK;
+}
+
 int npfem_batch_config(npfem_batch b, int32_t cls, int32_t out[4]) {
   if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
   if (!out || cls < 0 || cls >= (int)b->cls.size())

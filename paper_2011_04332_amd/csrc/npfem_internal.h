@@ -139,6 +139,14 @@ hipError_t launch_residual(const ClassSlice<T>& cs, const T* rhs, const T* delta
                            const T* delta0, T* res, const T* weights, float* colmax,
                            const float* need, double need_factor, double need_thr, double h,
                            hipStream_t st);
+// Cells the static staging buffer of npfem_get_volume_noalloc holds, and the
+// devices whose addresses of it are kept.
+constexpr int kVolumeScratchCells = 1 << 16;
+constexpr int kMaxDevices = 64;
+// Device address of that buffer on the current device (looked up once per
+// device with hipGetSymbolAddress).
+hipError_t volume_scratch(double** out);
+
 template <typename T>
 hipError_t launch_volume(const ClassSlice<T>& cs, const T* pos, long long sumN, double* out,
                          hipStream_t st);
