@@ -190,7 +190,7 @@ def step(ct: TorchCell, x, v, f, w, m, h, n_iter, chol=None):
 
 
 def rollout_grad(o: ops_mod.CellOperators, weights, mass, dt, x0, v0, f, target, n_iter,
-                 n_steps, round_state=None):
+                 n_steps, round_state=None, states=None, x_final=None):
     """L = sum |x_T - target|^2 and its gradients.
 
     Returns (L, dL/dw [4], dL/df [N,3], dL/dx0 [N,3], dL/dv0 [N,3]), float64
@@ -201,20 +201,32 @@ def rollout_grad(o: ops_mod.CellOperators, weights, mass, dt, x0, v0, f, target,
     i.e. the exact gradient along the trajectory of a solver that stores its
     state in that type (the step itself stays FP64). The difference from the
     unrounded gradient measures how much the storage rounding alone moves the
-    gradient."""
+    gradient.
+
+    states, x_final: differentiate along a given trajectory instead of the
+    oracle's own: states[n] = (x_n, v_n) at the start of step n (n_steps of
+    them) and x_final the positions after the last step, e.g. the states a
+    reduced-precision solver went through. Each step's derivative is taken
+    at the given state (FP64), so the result is the exact gradient of the
+    composed step maps along that trajectory."""
     ct = TorchCell(o)
     m, h = float(mass), float(dt)
     w_val = _t(np.asarray(weights, dtype=np.float64))
     f_val = _t(f)
-    states = []
-    x, v = _t(x0), _t(v0)
-    with torch.no_grad():
-        chol = system_factor(ct, w_val, m, h)
-        for _ in range(n_steps):
-            states.append((x, v))
-            x, v = step(ct, x, v, f_val, w_val, m, h, n_iter, chol)
-            if round_state is not None:
-                x, v = x.to(round_state).to(DT), v.to(round_state).to(DT)
+    if states is not None:
+        assert len(states) == n_steps and x_final is not None
+        states = [(_t(a), _t(b)) for a, b in states]
+        x = _t(x_final)
+    else:
+        states = []
+        x, v = _t(x0), _t(v0)
+        with torch.no_grad():
+            chol = system_factor(ct, w_val, m, h)
+            for _ in range(n_steps):
+                states.append((x, v))
+                x, v = step(ct, x, v, f_val, w_val, m, h, n_iter, chol)
+                if round_state is not None:
+                    x, v = x.to(round_state).to(DT), v.to(round_state).to(DT)
     loss = float(((x - _t(target)) ** 2).sum())
     gx = 2.0 * (x - _t(target))
     gv = torch.zeros_like(gx)

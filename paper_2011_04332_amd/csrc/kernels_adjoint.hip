@@ -18,6 +18,7 @@
 // points. Element VJPs go through LDS and are gathered per vertex in a fixed
 // order, as in the forward kernel.
 //
+// The element arithmetic runs in FP64 also for FP32 state (see the kernel).
 // The weight-gradient residuals P_i(q) - S_i q' are formed in displacement
 // form, (P_i(q) - S_i q) + S_i (q - q') with q - q' = delta^k - delta^{k+1}
 // taken from the delta columns and the volume's P(q) - q = lam grad V taken
@@ -50,7 +51,11 @@ template <typename T, int BLOCK, int VPT>
 __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
   extern __shared__ double smem_adj[];
   constexpr int NW = BLOCK / kWave;
-  constexpr int NEWTON = sizeof(T) == 8 ? 4 : 3;
+  // Element arithmetic (projections, their VJPs and the weight-gradient
+  // residuals) in FP64 for both state types: near rest the residuals
+  // P_i(q) - S_i q are ~1e-3 of the O(1) terms they are formed from, and
+  // the weight gradients sum them against lam with heavy cancellation.
+  using A = double;
   const AdjArgs<T>& a = L.a;
   const ClassView<T>& cv = a.cs.cv;
   const int N = cv.N, Npad = cv.Npad, F = cv.F, E = cv.E, DT = cv.DT, DH = cv.DH;
@@ -201,36 +206,38 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
       if (t + BLOCK < base + nt) idn = cv.tri_v[t + BLOCK];
       const V4<T> r0 = reinterpret_cast<const V4<T>*>(cv.tri_rec)[2 * t];
       const V4<T> r1 = reinterpret_cast<const V4<T>*>(cv.tri_rec)[2 * t + 1];
-      const T g00 = r0.x, g01 = r0.y, g10 = r0.z, g11 = r0.w, g20 = r1.x, g21 = r1.y;
-      const T area = r1.z;
-      T fq[3][2], fd[3][2], fl[3][2];  // F(q), F(q - q'), F(lam)
+      const A g00 = r0.x, g01 = r0.y, g10 = r0.z, g11 = r0.w, g20 = r1.x, g21 = r1.y;
+      const A area = r1.z;
+      A fq[3][2], fd[3][2], fl[3][2];  // F(q), F(q - q'), F(lam)
       {
         const V4<T> qa = qs[id.x], qb = qs[id.y], qc = qs[id.z];
         const V4<T> ua = dds[id.x], ub = dds[id.y], uc = dds[id.z];
         const V4<T> la = ls[id.x], lb = ls[id.y], lcc = ls[id.z];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          fq[d][0] = comp(qa, d) * g00 + comp(qb, d) * g10 + comp(qc, d) * g20;
-          fq[d][1] = comp(qa, d) * g01 + comp(qb, d) * g11 + comp(qc, d) * g21;
-          fd[d][0] = comp(ua, d) * g00 + comp(ub, d) * g10 + comp(uc, d) * g20;
-          fd[d][1] = comp(ua, d) * g01 + comp(ub, d) * g11 + comp(uc, d) * g21;
-          fl[d][0] = comp(la, d) * g00 + comp(lb, d) * g10 + comp(lcc, d) * g20;
-          fl[d][1] = comp(la, d) * g01 + comp(lb, d) * g11 + comp(lcc, d) * g21;
+          // F(q) from the edge vectors, as in the forward step
+          const A e1 = (A)comp(qb, d) - (A)comp(qa, d), e2 = (A)comp(qc, d) - (A)comp(qa, d);
+          fq[d][0] = e1 * g10 + e2 * g20;
+          fq[d][1] = e1 * g11 + e2 * g21;
+          fd[d][0] = (A)comp(ua, d) * g00 + (A)comp(ub, d) * g10 + (A)comp(uc, d) * g20;
+          fd[d][1] = (A)comp(ua, d) * g01 + (A)comp(ub, d) * g11 + (A)comp(uc, d) * g21;
+          fl[d][0] = (A)comp(la, d) * g00 + (A)comp(lb, d) * g10 + (A)comp(lcc, d) * g20;
+          fl[d][1] = (A)comp(la, d) * g01 + (A)comp(lb, d) * g11 + (A)comp(lcc, d) * g21;
         }
       }
-      TriProj<T> P;
-      project_triangle<T, NEWTON>(fq, P, bad);
-      T es = T(0), ea = T(0);
-      T gs2[3][2], ga2[3][2], fb[3][2];
+      TriProj<A> P;
+      project_triangle<A, 4>(fq, P, bad);
+      A es = A(0), ea = A(0);
+      A gs2[3][2], ga2[3][2], fb[3][2];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
           es += fl[d][k] * ((P.ps[d][k] - fq[d][k]) + fd[d][k]);
           ea += fl[d][k] * ((P.pa[d][k] - fq[d][k]) + fd[d][k]);
-          gs2[d][k] = ws * area * fl[d][k];
-          ga2[d][k] = wa * area * fl[d][k];
-          fb[d][k] = T(0);
+          gs2[d][k] = (A)ws * area * fl[d][k];
+          ga2[d][k] = (A)wa * area * fl[d][k];
+          fb[d][k] = A(0);
         }
       }
       wacc[0] += (double)(area * es);
@@ -240,8 +247,8 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
       T* wsl = work + 6 * (t - base);
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        wsl[2 * d] = fb[d][0];
-        wsl[2 * d + 1] = fb[d][1];
+        wsl[2 * d] = T(fb[d][0]);
+        wsl[2 * d + 1] = T(fb[d][1]);
       }
     }
     __syncthreads();
@@ -287,34 +294,37 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
       if (e + BLOCK < base + ne) idn = cv.hin_v[e + BLOCK];
       const V4<T> r0 = reinterpret_cast<const V4<T>*>(cv.hin_rec)[2 * e];
       const V4<T> r1 = reinterpret_cast<const V4<T>*>(cv.hin_rec)[2 * e + 1];
-      const T k0 = r0.x, k1 = r0.y, k2 = r0.z, k3 = r0.w, ce = r1.x, rr = r1.y;
-      T yq[3], yd[3], yl[3];  // y(q), y(q - q'), y(lam)
+      const A k0 = r0.x, k1 = r0.y, k2 = r0.z, k3 = r0.w, ce = r1.x, rr = r1.y;
+      A yq[3], yd[3], yl[3];  // y(q), y(q - q'), y(lam)
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        yq[d] = k0 * comp(qs[id.x], d) + k1 * comp(qs[id.y], d) + k2 * comp(qs[id.z], d) +
-                k3 * comp(qs[id.w], d);
-        yd[d] = k0 * comp(dds[id.x], d) + k1 * comp(dds[id.y], d) + k2 * comp(dds[id.z], d) +
-                k3 * comp(dds[id.w], d);
-        yl[d] = k0 * comp(ls[id.x], d) + k1 * comp(ls[id.y], d) + k2 * comp(ls[id.z], d) +
-                k3 * comp(ls[id.w], d);
+        // y(q) from the differences to q_i, as in the forward step
+        const A qi_d = (A)comp(qs[id.x], d);
+        yq[d] = k1 * ((A)comp(qs[id.y], d) - qi_d) + k2 * ((A)comp(qs[id.z], d) - qi_d) +
+                k3 * ((A)comp(qs[id.w], d) - qi_d);
+        yd[d] = k0 * (A)comp(dds[id.x], d) + k1 * (A)comp(dds[id.y], d) +
+                k2 * (A)comp(dds[id.z], d) + k3 * (A)comp(dds[id.w], d);
+        yl[d] = k0 * (A)comp(ls[id.x], d) + k1 * (A)comp(ls[id.y], d) +
+                k2 * (A)comp(ls[id.z], d) + k3 * (A)comp(ls[id.w], d);
       }
-      const T n2 = yq[0] * yq[0] + yq[1] * yq[1] + yq[2] * yq[2];
-      const T in = n2 > T(0) ? f_rsq(n2) : T(0);
-      const T sc = n2 > T(0) ? rr * in : T(1);
-      T eb = T(0);
+      const A n2 = yq[0] * yq[0] + yq[1] * yq[1] + yq[2] * yq[2];
+      const A in = n2 > A(0) ? f_rsq(n2) : A(0);
+      const A sc = n2 > A(0) ? rr * in : A(1);
+      A eb = A(0);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) eb += yl[d] * ((sc - T(1)) * yq[d] + yd[d]);
+      for (int d = 0; d < 3; ++d) eb += yl[d] * ((sc - A(1)) * yq[d] + yd[d]);
       wacc[2] += (double)(ce * eb);
       // Pb = r y/|y|: Jacobian (r/|y|)(I - yh yh^T), symmetric
-      const T wc = wb * ce;
-      T pb[3] = {wc * yl[0], wc * yl[1], wc * yl[2]};
+      const A wc = (A)wb * ce;
+      A pb[3] = {wc * yl[0], wc * yl[1], wc * yl[2]};
       V4<T> yb;
-      if (n2 > T(0)) {
-        const T yh0 = yq[0] * in, yh1 = yq[1] * in, yh2 = yq[2] * in;
-        const T dp = yh0 * pb[0] + yh1 * pb[1] + yh2 * pb[2];
-        yb = V4<T>{sc * (pb[0] - yh0 * dp), sc * (pb[1] - yh1 * dp), sc * (pb[2] - yh2 * dp), T(0)};
+      if (n2 > A(0)) {
+        const A yh0 = yq[0] * in, yh1 = yq[1] * in, yh2 = yq[2] * in;
+        const A dp = yh0 * pb[0] + yh1 * pb[1] + yh2 * pb[2];
+        yb = V4<T>{T(sc * (pb[0] - yh0 * dp)), T(sc * (pb[1] - yh1 * dp)),
+                   T(sc * (pb[2] - yh2 * dp)), T(0)};
       } else {
-        yb = V4<T>{pb[0], pb[1], pb[2], T(0)};
+        yb = V4<T>{T(pb[0]), T(pb[1]), T(pb[2]), T(0)};
       }
       ys[e - base] = yb;
     }

@@ -160,12 +160,18 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
       const T g00 = r0.x, g01 = r0.y, g10 = r0.z, g11 = r0.w, g20 = r1.x, g21 = r1.y;
       const T area = r1.z;
       const V4<T> qa = qs[id.x], qb = qs[id.y], qc = qs[id.z];
+      // F from the edge vectors (the rows of G sum to zero): exactly
+      // translation-invariant with the rounded G, and the differences of
+      // nearby coordinates are exact, so F carries the rounding of O(1)
+      // products instead of the cancellation of O(R/edge) terms
+      (void)g00;
+      (void)g01;
       T fq[3][2];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const T q0 = comp(qa, d), q1 = comp(qb, d), q2 = comp(qc, d);
-        fq[d][0] = q0 * g00 + q1 * g10 + q2 * g20;
-        fq[d][1] = q0 * g01 + q1 * g11 + q2 * g21;
+        const T e1 = comp(qb, d) - comp(qa, d), e2 = comp(qc, d) - comp(qa, d);
+        fq[d][0] = e1 * g10 + e2 * g20;
+        fq[d][1] = e1 * g11 + e2 * g21;
       }
       TriProj<T> P;
       project_triangle<T, NEWTON, false>(fq, P, bad);
@@ -296,7 +302,7 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
   // inertia term of the own vertices, cterm - (m/h^2) delta, loaded here so
   // that the loads are in flight during the hinge phase (barriers wait for
   // LDS only)
-  const T mh2 = T(a.m / (a.h * a.h));
+  const T mh2 = T(a.mdelta);
   T ct[VPT][3];
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
@@ -323,10 +329,14 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
       }
       const T k0 = r0.x, k1 = r0.y, k2 = r0.z, k3 = r0.w, ce = r1.x, rr = r1.y;
       const V4<T> qi = qs[id.x], qj = qs[id.y], qk = qs[id.z], ql = qs[id.w];
+      // y from the differences to q_i (the stencil weights sum to zero), as F
+      (void)k0;
       T yq[3];
 #pragma unroll
-      for (int d = 0; d < 3; ++d)
-        yq[d] = k0 * comp(qi, d) + k1 * comp(qj, d) + k2 * comp(qk, d) + k3 * comp(ql, d);
+      for (int d = 0; d < 3; ++d) {
+        const T qi_d = comp(qi, d);
+        yq[d] = k1 * (comp(qj, d) - qi_d) + k2 * (comp(qk, d) - qi_d) + k3 * (comp(ql, d) - qi_d);
+      }
       const T n2 = yq[0] * yq[0] + yq[1] * yq[1] + yq[2] * yq[2];
       const T sc = n2 > T(0) ? rr * f_rsq(n2) : T(1);
       const T wc = wb * ce;

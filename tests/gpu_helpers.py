@@ -48,7 +48,8 @@ def oracle_cells(susp, cells, n_steps=None, n_iter=None, dt=None):
     for c in cells:
         mc, x0, v0, f, w = susp.cell_arrays(int(c))
         o = S.operators_for(mc)
-        prm = S.Params(tuple(w), mc.mass, susp.dt if dt is None else dt)
+        prm = S.Params(tuple(w), mc.mass, susp.dt if dt is None else dt,
+                       tuple(getattr(mc, "damping", (0.0, 0.0))))
         cs = S.CellSolver(o, prm)
         out[int(c)] = cs.rollout(x0, v0, f, susp.n_iter if n_iter is None else n_iter,
                                  susp.n_steps if n_steps is None else n_steps)
@@ -63,3 +64,19 @@ def cell_error(susp, x_gpu, cell, x_ref):
 
 def max_error(susp, x_gpu, ref):
     return max(cell_error(susp, x_gpu, c, xr) for c, (xr, _) in ref.items())
+
+
+def reverse_along(args):
+    """Worker (spawned process): the oracle's FP64 reverse-mode gradient of
+    one cell along the trajectory another solver went through."""
+    import os
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    import torch
+    torch.set_num_threads(1)
+    from oracle import reverse as R
+    susp, c, tgt, states, x_final = args
+    mc, x0, v0, f, w = susp.cell_arrays(int(c))
+    o = S.operators_for(mc)
+    _, gw, gf, _, _ = R.rollout_grad(o, w, mc.mass, susp.dt, x0, v0, f, tgt, susp.n_iter,
+                                     susp.n_steps, states=states, x_final=x_final)
+    return int(c), gw, gf

@@ -182,3 +182,20 @@ def test_stored_reverse_gradient_recomputes():
     new = M.one_cell(row["cell"])
     assert np.allclose(new["dw"], row["dw"], rtol=1e-12, atol=0)
     assert np.allclose(new["df_sample"], row["df_sample"], rtol=1e-12, atol=0)
+
+
+def test_given_trajectory_equals_own_trajectory():
+    """Differentiating along the oracle's own recorded states gives the
+    oracle's gradient bit for bit (the path the GPU-trajectory check uses)."""
+    s, mc, x0, v0, f, w, tgt = _cell(True, n_steps=2, n_iter=2)
+    o = S.operators_for(mc)
+    cs = S.CellSolver(o, S.Params(tuple(w), mc.mass, s.dt))
+    states, x, v = [], x0, v0
+    for _ in range(2):
+        states.append((x, v))
+        x, v, _ = cs.step(x, v, f, 2)
+    L1, gw1, gf1, *_ = R.rollout_grad(o, w, mc.mass, s.dt, x0, v0, f, tgt, 2, 2)
+    L2, gw2, gf2, *_ = R.rollout_grad(o, w, mc.mass, s.dt, x0, v0, f, tgt, 2, 2,
+                                      states=states, x_final=x)
+    assert abs(L1 - L2) <= 1e-12 * L1
+    assert np.allclose(gw1, gw2, rtol=1e-10, atol=0) and np.allclose(gf1, gf2, rtol=1e-10, atol=1e-14)
