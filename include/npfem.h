@@ -146,7 +146,9 @@ int npfem_mesh_system_matrix(npfem_mesh m, const double* weights4, double dt, do
  *                 updated in place by npfem_step
  *   opt           options (NULL = FP32, defaults)
  * Allocates device workspace; the FP64 factorisation happens at the first
- * step (it depends on the time step). Errors: INVALID_ARG, HIP, OOM. */
+ * step (it depends on the time step). Errors: INVALID_ARG (also for an FP64
+ * batch with a mesh of more than 2550 vertices, whose local step does not fit
+ * the 160 KB of LDS of a CU), HIP, OOM. */
 int npfem_create_batch(const npfem_mesh* meshes, int32_t n_meshes, const int32_t* cell_mesh,
                        int32_t n_cells, const double* cell_weights, void* pos, void* vel,
                        const npfem_options* opt, npfem_batch* out);
@@ -171,6 +173,23 @@ int npfem_step(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter)
  * Errors: INVALID_ARG (non-finite or negative weights, or weights too far
  * from nominal for the sweeps to converge), HIP. */
 int npfem_set_weights(npfem_batch b, const double* cell_weights);
+
+/* Viscous damping of mesh class cls (-1: every class): a damping force
+ * -C v with C = alpha m I + beta ((w_s + w_a) L_tri + w_b L_bend), mass- and
+ * stiffness-proportional (the material's viscosity parameters Calpha and
+ * Cbeta; the elastodynamics equation with a viscous term, Introduction),
+ * taken implicitly at the end-of-step velocity: the step minimises its
+ * objective plus (1/2h)(q - x)^T C (q - x), so the global system becomes
+ * A + C/h and the first iterate (s + alpha h x)/(1 + alpha h). L_tri and
+ * L_bend are the cell's strain/area and bending Laplacians (with its own
+ * weights), so C has no net force and does not resist rigid translation.
+ * 0, 0 (the default) is the undamped step. The next step refactors and
+ * re-captures (slow); a stiffness-proportional term allocates one column
+ * buffer at the first call that sets it. npfem_rollout_adjoint does not
+ * cover damping (INVALID_ARG), and the energy of NPFEM_OPT_ENERGY omits the
+ * damping term. Synchronises. Errors: INVALID_ARG (class out of range,
+ * negative or non-finite coefficients), HIP, OOM. */
+int npfem_set_damping(npfem_batch b, int32_t cls, double alpha, double beta);
 
 /* Differentiable rollout: n_steps calls of npfem_step under constant forces,
  * storing (positions, velocities) before every ckpt_every-th step as

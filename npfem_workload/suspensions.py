@@ -45,6 +45,7 @@ class MeshClass:
     tris: np.ndarray  # [F, 3] int32
     weights: tuple = NOMINAL_WEIGHTS
     mass: float = VERTEX_MASS
+    damping: tuple = (0.0, 0.0)  # (alpha, beta) viscous damping coefficients
 
     @property
     def n_verts(self) -> int:

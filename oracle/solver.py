@@ -36,6 +36,16 @@ class Params:
     weights: tuple  # (w_stretch, w_area, w_bend, w_volume)
     mass: float
     dt: float
+    damping: tuple = (0.0, 0.0)  # (alpha, beta): Rayleigh-type viscous damping
+
+
+def damping_stiffness(o: ops_mod.CellOperators, weights) -> np.ndarray:
+    """K_d = (w_s + w_a) L_tri + w_b L_bend: the constraint stiffness without
+    the volume term's identity (it vanishes on rigid translations, which the
+    stiffness-proportional damping must not resist)."""
+    ws, wa, wb, _ = (float(w) for w in weights)
+    Lt, Lb = ops_mod.laplacians(o)
+    return (ws + wa) * Lt + wb * Lb
 
 
 def rhs(o: ops_mod.CellOperators, P: dict, s: np.ndarray, prm: Params) -> np.ndarray:
@@ -57,9 +67,14 @@ def rhs(o: ops_mod.CellOperators, P: dict, s: np.ndarray, prm: Params) -> np.nda
     return b
 
 
-def energy(o: ops_mod.CellOperators, q: np.ndarray, s: np.ndarray, P: dict, prm: Params) -> float:
+def energy(o: ops_mod.CellOperators, q: np.ndarray, s: np.ndarray, P: dict, prm: Params,
+           x=None, C=None) -> float:
+    """The step's objective at q (with the projections P = P(q)); with a
+    damping matrix C and the step's start x, plus (1/2h)(q - x)^T C (q - x)."""
     ws, wa, wb, wv = prm.weights
     e = 0.5 * prm.mass / prm.dt ** 2 * np.sum((q - s) ** 2)
+    if C is not None:
+        e += 0.5 / prm.dt * float(np.sum((q - x) * (C @ (q - x))))
     dF_s = np.sum((P["F"] - P["Ps"]) ** 2, axis=(1, 2))
     dF_a = np.sum((P["F"] - P["Pa"]) ** 2, axis=(1, 2))
     e += np.sum(0.5 * o.area * (ws * dF_s + wa * dF_a))
@@ -69,12 +84,29 @@ def energy(o: ops_mod.CellOperators, q: np.ndarray, s: np.ndarray, P: dict, prm:
 
 
 class CellSolver:
-    """Factorised system for one (mesh class, weights, mass, dt)."""
+    """Factorised system for one (mesh class, weights, mass, dt, damping).
+
+    Viscoelastic reading (the elastodynamics equation with a viscous term,
+    Introduction; the viscosity parameters Calpha and Cbeta of the material,
+    sections "RBC collision at an obstacle" and "Setting up new materials"):
+    a damping force -C v with C = alpha m I + beta K_d (mass- and
+    stiffness-proportional, K_d = damping_stiffness), taken implicitly at
+    v_{n+1} = (q - x_n)/h. It adds (1/2h)(q - x_n)^T C (q - x_n) to the
+    step's objective, so the system matrix becomes A + C/h and the
+    right-hand side gains C x_n / h; the local step is unchanged. The first
+    iterate minimises the inertia and mass-damping terms alone,
+    q^0 = (s + alpha h x_n)/(1 + alpha h) (s itself without damping), which
+    keeps the momentum balance exact at every iteration count."""
 
     def __init__(self, o: ops_mod.CellOperators, prm: Params):
         self.o = o
         self.prm = prm
         self.A = ops_mod.system_matrix(o, prm.weights, prm.mass, prm.dt)
+        alpha, beta = prm.damping
+        self.C = None
+        if alpha != 0.0 or beta != 0.0:
+            self.C = alpha * prm.mass * np.eye(o.n_verts) + beta * damping_stiffness(o, prm.weights)
+            self.A = self.A + self.C / prm.dt
         self.chol = ops_mod.factor(self.A)
 
     def step(self, x, v, f, n_iter, record_energy=False):
@@ -84,17 +116,21 @@ class CellSolver:
         v = (q - x) / h, no damping."""
         h, m = self.prm.dt, self.prm.mass
         s = x + h * v + (h * h / m) * f
-        q = s.copy()
+        alpha = self.prm.damping[0]
+        q = s.copy() if alpha == 0.0 else (s + alpha * h * x) / (1.0 + alpha * h)
         energies = []
+        cx = None if self.C is None else (self.C @ x) / h
         for _ in range(n_iter):
             P = proj.local_step(q, self.o)
             if record_energy:
-                energies.append(energy(self.o, q, s, P, self.prm))
+                energies.append(energy(self.o, q, s, P, self.prm, x, self.C))
             b = rhs(self.o, P, s, self.prm)
+            if cx is not None:
+                b = b + cx
             q = scipy.linalg.cho_solve(self.chol, b)
         if record_energy:
             P = proj.local_step(q, self.o)
-            energies.append(energy(self.o, q, s, P, self.prm))
+            energies.append(energy(self.o, q, s, P, self.prm, x, self.C))
         return q, (q - x) / h, energies
 
     def rollout(self, x0, v0, f, n_iter, n_steps, forces_per_step=None):
@@ -121,7 +157,8 @@ def run_cell(susp, c: int, n_steps=None, n_iter=None, dt=None):
     """Roll out one cell of a suspension; returns (x [N,3], v [N,3]) local coords."""
     mc, x0, v0, f, w = susp.cell_arrays(c)
     o = operators_for(mc)
-    prm = Params(tuple(w), mc.mass, susp.dt if dt is None else dt)
+    prm = Params(tuple(w), mc.mass, susp.dt if dt is None else dt,
+                 tuple(getattr(mc, "damping", (0.0, 0.0))))
     solver = CellSolver(o, prm)
     return solver.rollout(x0, v0, f, susp.n_iter if n_iter is None else n_iter,
                           susp.n_steps if n_steps is None else n_steps)

@@ -39,6 +39,7 @@ EXPORTED = [
     "npfem_create_batch",
     "npfem_step",
     "npfem_set_weights",
+    "npfem_set_damping",
     "npfem_rollout",
     "npfem_rollout_adjoint",
     "npfem_sync_status",
@@ -99,6 +100,7 @@ def load() -> ctypes.CDLL:
                                        ctypes.POINTER(P)]
     lib.npfem_step.argtypes = [P, P, D, I32]
     lib.npfem_set_weights.argtypes = [P, P]
+    lib.npfem_set_damping.argtypes = [P, I32, D, D]
     lib.npfem_rollout.argtypes = [P, P, D, I32, I32, I32]
     lib.npfem_rollout_adjoint.argtypes = [P, P, P, P, P, P, P]
     lib.npfem_sync_status.argtypes = [P]

@@ -14,19 +14,20 @@ namespace npfem {
 
 // Predict (start of a time step, delta form). With s = x + h v + (h^2/m) f:
 //   cterm  = (m/h^2)(s - x) = (m/h) v + f   (constant over the PD iterations)
-//   delta0 = s - x = (h^2/m) cterm          (q^0 = s)
+//   delta0 = (s - x)/(1 + alpha h)          (q^0 = s; with mass-proportional
+//            damping alpha the minimiser of the inertia and damping terms)
 template <typename T>
 __global__ void __launch_bounds__(256) predict_kernel(ClassSlice<T> cs, const T* __restrict__ pos,
                                                       const T* __restrict__ vel,
                                                       const T* __restrict__ force, long long sumN,
                                                       T* __restrict__ delta, T* __restrict__ cterm,
-                                                      int* status, double h) {
+                                                      int* status, double h, double alpha) {
   const int lc = blockIdx.x;
   const int N = cs.cv.N, Npad = cs.cv.Npad;
   const long long vb = cs.vert0 + (long long)lc * N;
   const long long cb = cs.elem0 + 3LL * lc * Npad;
   const double m = (double)cs.mass;
-  const double mh = m / h, hm = h * h / m;
+  const double mh = m / h, hm = h * h / m, ds = 1.0 / (1.0 + alpha * h);
   int bad = 0;
   for (int v = threadIdx.x; v < Npad; v += blockDim.x) {
 #pragma unroll
@@ -39,7 +40,7 @@ __global__ void __launch_bounds__(256) predict_kernel(ClassSlice<T> cs, const T*
         bad |= !(isfinite(x) && isfinite(u) && isfinite(f));
         const double cd = mh * (double)u + (double)f;
         c = T(cd);
-        dl = T(h * (double)u + hm * (double)f);
+        dl = T((h * (double)u + hm * (double)f) * ds);
       }
       cterm[cb + d * Npad + v] = c;
       delta[cb + d * Npad + v] = dl;
@@ -70,8 +71,10 @@ __global__ void __launch_bounds__(256) update_kernel(ClassSlice<T> cs, T* __rest
 
 // Refinement residual res = r - A_c (delta - delta0) for each cell (delta0 the
 // iterate the solve started from, nullptr for none), with the per-cell
-// system A_c = (m/h^2 + w_v) I + (w_s + w_a) L_tri + w_b L_bend (fixed-width
-// rows of the two Laplacians, shared by the class). One workgroup handles CPB
+// matrix A_c = (cmass m + cvol w_v) I + clap ((w_s + w_a) L_tri + w_b L_bend)
+// (fixed-width rows of the two Laplacians, shared by the class): the
+// system matrix (cmass = 1/h^2, clap = cvol = 1; damped: cmass = (1 + alpha
+// h)/h^2, clap = 1 + beta/h), or a damping term (cvol = 0). One workgroup handles CPB
 // cells with one thread per row (up to 768 rows at a time): the row's table
 // entries are fetched once and applied to all CPB cells, so the class tables
 // are read from L2 once per CPB cells, and a thread has three round trips to
@@ -95,7 +98,7 @@ __global__ void __launch_bounds__(kResidualBlock) residual_kernel(
     ClassSlice<T> cs, const T* __restrict__ rhs, const T* __restrict__ delta,
     const T* __restrict__ delta0, T* __restrict__ res,
     const T* __restrict__ weights, float* __restrict__ colmax, const float* __restrict__ need,
-    double need_factor, double need_thr, double h) {
+    double need_factor, double need_thr, double cmass, double clap, double cvol) {
   extern __shared__ double smem_res[];
   unsigned* cmx = reinterpret_cast<unsigned*>(smem_res);  // [3 CPB]
   T* sd = reinterpret_cast<T*>(smem_res + (3 * CPB + 1) / 2);  // [CPB][3][N + 1]
@@ -154,9 +157,9 @@ __global__ void __launch_bounds__(kResidualBlock) residual_kernel(
     double w[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) w[k] = weights ? (double)weights[4 * cell + k] : (double)cs.w_nom[k];
-    diag[c] = (double)cs.mass / (h * h) + w[3];
-    wt[c] = w[0] + w[1];
-    wb[c] = w[2];
+    diag[c] = cmass * (double)cs.mass + cvol * w[3];
+    wt[c] = clap * (w[0] + w[1]);
+    wb[c] = clap * w[2];
   }
   float cm[CPB][3];
 #pragma unroll
@@ -256,10 +259,10 @@ __global__ void __launch_bounds__(256) volume_kernel(ClassSlice<T> cs, const T* 
 template <typename T>
 hipError_t launch_predict(const ClassSlice<T>& cs, const T* pos, const T* vel, const T* force,
                           long long sumN, T* delta, T* cterm, int* status, double h,
-                          hipStream_t st) {
+                          double alpha, hipStream_t st) {
   if (cs.n_cells == 0) return hipSuccess;
   hipLaunchKernelGGL(predict_kernel<T>, dim3(cs.n_cells), dim3(256), 0, st, cs, pos, vel, force,
-                     sumN, delta, cterm, status, h);
+                     sumN, delta, cterm, status, h, alpha);
   return hipGetLastError();
 }
 
@@ -282,15 +285,16 @@ static size_t residual_smem(int N) {
 template <typename T>
 hipError_t launch_residual(const ClassSlice<T>& cs, const T* rhs, const T* delta,
                            const T* delta0, T* res, const T* weights, float* colmax,
-                           const float* need, double need_factor, double need_thr, double h,
-                           hipStream_t st) {
+                           const float* need, double need_factor, double need_thr,
+                           double cmass, double clap, double cvol, hipStream_t st) {
   if (cs.n_cells == 0) return hipSuccess;
   const int N = cs.cv.N;
   const int block = std::min(kResidualBlock, (cs.cv.Npad + 63) / 64 * 64);
   const size_t cap = 64 * 1024;
   auto go = [&](auto kern, int cpb, size_t smem) {
     hipLaunchKernelGGL(kern, dim3((cs.n_cells + cpb - 1) / cpb), dim3(block), smem, st, cs, rhs,
-                       delta, delta0, res, weights, colmax, need, need_factor, need_thr, h);
+                       delta, delta0, res, weights, colmax, need, need_factor, need_thr, cmass,
+                       clap, cvol);
     return hipGetLastError();
   };
   if constexpr (sizeof(T) == 4) {  // (6 FP64 cells would not fit the registers)
@@ -336,12 +340,12 @@ hipError_t launch_volume(const ClassSlice<T>& cs, const T* pos, long long sumN, 
 
 #define NPFEM_INST(T)                                                                            \
   template hipError_t launch_predict<T>(const ClassSlice<T>&, const T*, const T*, const T*,      \
-                                        long long, T*, T*, int*, double, hipStream_t);           \
+                                        long long, T*, T*, int*, double, double, hipStream_t);   \
   template hipError_t launch_update<T>(const ClassSlice<T>&, T*, T*, long long, const T*, double, \
                                        hipStream_t);                                             \
   template hipError_t launch_residual<T>(const ClassSlice<T>&, const T*, const T*, const T*, T*, \
                                          const T*, float*, const float*, double, double, double, \
-                                         hipStream_t);                                           \
+                                         double, double, hipStream_t);                           \
   template hipError_t launch_volume<T>(const ClassSlice<T>&, const T*, long long, double*,       \
                                        hipStream_t);
 NPFEM_INST(float)

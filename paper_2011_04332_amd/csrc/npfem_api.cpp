@@ -84,6 +84,14 @@ struct ClassState {
   int local_block = 256;
   int gemm_tile = 3;
   int DT = 0, DH = 0, DL = 0;  // padded incidence and Laplacian widths
+  // viscous damping C = alpha m I + beta ((w_s + w_a) L_tri + w_b L_bend)
+  // (npfem_set_damping); 0, 0 = none
+  double alpha = 0.0, beta_d = 0.0;
+  // the damped system A + C/h is the undamped one with the mass and the
+  // stretch/area/bend weights scaled: these are the scales at time step h
+  double mass_scale(double h) const { return 1.0 + alpha * h; }
+  double lap_scale(double h) const { return 1.0 + beta_d / h; }
+  double hm_eff(double h) const { return h * h / (mat.vertex_mass * mass_scale(h)); }
 };
 
 }  // namespace
@@ -113,6 +121,7 @@ struct npfem_batch_s {
   void* cterm = nullptr;
   void* rhs = nullptr;
   void* res = nullptr;
+  void* damp = nullptr;         // right-hand side with the stiffness damping term (columns)
   float* colmax = nullptr;      // max |r| per column (16-bit products)
   float* colmax_res = nullptr;  // max |res| per column of the correction sweeps
   int* status = nullptr;
@@ -484,11 +493,13 @@ int choose_refine(npfem_batch_s* b, double dt, int* out) {
   if (b->per_cell) {
     for (const ClassState& c : b->cls) {
       const double w0[4] = {c.mat.w_stretch, c.mat.w_area, c.mat.w_bend, c.mat.w_volume};
-      const double lmin = c.mat.vertex_mass / (dt * dt) + c.mat.w_volume;
+      const double lmin = c.mat.vertex_mass * c.mass_scale(dt) / (dt * dt) + c.mat.w_volume;
+      const double ls = c.lap_scale(dt);
       for (int i = 0; i < c.n_cells; ++i) {
         const double* w = &b->weights_host[4 * (size_t)(c.cell0 + i)];
-        const double dev = std::fabs(w[0] + w[1] - w0[0] - w0[1]) * c.ops.norm_t +
-                           std::fabs(w[2] - w0[2]) * c.ops.norm_b + std::fabs(w[3] - w0[3]);
+        const double dev = ls * (std::fabs(w[0] + w[1] - w0[0] - w0[1]) * c.ops.norm_t +
+                                 std::fabs(w[2] - w0[2]) * c.ops.norm_b) +
+                           std::fabs(w[3] - w0[3]);
         rho_w = std::max(rho_w, dev / lmin);
       }
     }
@@ -575,8 +586,11 @@ int factorise(npfem_batch_s* b, double dt) {
   for (auto& c : b->cls) {
     if (c.n_cells == 0) continue;
     hA.assign((size_t)c.Npad * c.Npad, 0.0);
-    const double w0[4] = {c.mat.w_stretch, c.mat.w_area, c.mat.w_bend, c.mat.w_volume};
-    dense_system_matrix(c.ops, w0, c.mat.vertex_mass, dt, hA.data(), c.Npad);
+    // (damped: A + C/h, the system matrix of the scaled mass and weights)
+    const double ls = c.lap_scale(dt);
+    const double w0[4] = {ls * c.mat.w_stretch, ls * c.mat.w_area, ls * c.mat.w_bend,
+                          c.mat.w_volume};
+    dense_system_matrix(c.ops, w0, c.mat.vertex_mass * c.mass_scale(dt), dt, hA.data(), c.Npad);
     int hfail = 0;
     e = hipMemcpy(dA, hA.data(), sizeof(double) * hA.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(dfail, 0, sizeof(int));
@@ -590,7 +604,7 @@ int factorise(npfem_batch_s* b, double dt) {
       cleanup();
       return fail(NPFEM_ERR_NOT_SPD, "system matrix of a %d-vertex class is not SPD", c.N);
     }
-    const double hm = dt * dt / c.mat.vertex_mass;
+    const double hm = c.hm_eff(dt);
     c.beta = 0.0;
     c.kappa = 0.0;
     if (b->gemm_kind != 1) {
@@ -683,7 +697,7 @@ int enqueue_solve(npfem_batch_s* b, ClassState& c, T* B, T* C, const T* D, doubl
   g.Npad = c.Npad;
   g.ncols = 3 * c.n_cells;
   g.mode = lp ? EPI_SPLIT_SET : EPI_SET;
-  g.hm = h * h / c.mat.vertex_mass;
+  g.hm = c.hm_eff(h);
   g.beta = c.beta;
   NPFEM_TIMED(NPFEM_KERNEL_GLOBAL, launch_gemm(b->gemm_kind, c.gemm_tile, g, st), "global step");
   // FP32 state with the automatic sweep count: sweep s + 1 runs for a cell
@@ -700,7 +714,8 @@ int enqueue_solve(npfem_batch_s* b, ClassState& c, T* B, T* C, const T* D, doubl
                 launch_residual<T>(slice_of<T>(c), B, C, D, res, w,
                                    (lp || adapt) ? b->colmax_res : nullptr,
                                    adapt ? b->colmax : nullptr, bound,
-                                   std::ldexp(1.0, -24) * c.r_rest, h, st),
+                                   std::ldexp(1.0, -24) * c.r_rest, c.mass_scale(h) / (h * h),
+                                   c.lap_scale(h), 1.0, st),
                 "residual");
     GemmArgs r = g;
     r.B = res + c.elem0;
@@ -735,7 +750,7 @@ int enqueue_class_step(npfem_batch_s* b, ClassState& c, T* pos, T* vel, const T*
   auto slot = [&](int k) { return dslots ? dslots[k] : (k & 1) ? delta2 : delta; };
   NPFEM_TIMED(NPFEM_KERNEL_PREDICT,
               launch_predict<T>(slice_of<T>(c), pos, vel, forces, b->sumN, slot(0), cterm,
-                                b->status, h, st),
+                                b->status, h, c.alpha, st),
               "predict");
   for (int it = 0; it < n_iter; ++it) {
     LocalArgs<T> a;
@@ -751,10 +766,22 @@ int enqueue_class_step(npfem_batch_s* b, ClassState& c, T* pos, T* vel, const T*
     a.status = b->status;
     a.h = h;
     a.m = c.mat.vertex_mass;
+    a.mdelta = c.mat.vertex_mass * c.mass_scale(h) / (h * h);
     a.max_vol_iter = b->max_vol_iter;
     set_volume_tolerances(a, c, b->fp64);
     NPFEM_TIMED(NPFEM_KERNEL_LOCAL, launch_local<T>(a, c.local_block, st), "local step");
-    const int rc = enqueue_solve<T>(b, c, rhs, slot(it + 1), slot(it), h, st, true);
+    T* B = rhs;
+    if (c.beta_d != 0.0) {
+      // stiffness-proportional damping: r -= (beta/h) K_d delta (K_d =
+      // (w_s + w_a) L_tri + w_b L_bend), the part of C delta/h that the local
+      // step does not form (its alpha m delta/h part is in mdelta)
+      B = static_cast<T*>(b->damp);
+      NPFEM_TIMED(NPFEM_KERNEL_RESIDUAL,
+                  launch_residual<T>(slice_of<T>(c), rhs, slot(it), nullptr, B, w, colmax,
+                                     nullptr, 0.0, 0.0, 0.0, c.beta_d / h, 0.0, st),
+                  "damping term");
+    }
+    const int rc = enqueue_solve<T>(b, c, B, slot(it + 1), slot(it), h, st, true);
     if (rc) return rc;
   }
   NPFEM_TIMED(NPFEM_KERNEL_UPDATE,
@@ -810,6 +837,7 @@ int enqueue_any(npfem_batch_s* b, const void* forces, double h, int n_iter, hipS
 
 int prepare_kernels(npfem_batch_s* b) {
   for (auto& c : b->cls) {
+    if (c.n_cells == 0) continue;
     hipError_t e = b->fp64 ? local_prepare<double>(slice_of<double>(c).cv, c.local_block)
                            : local_prepare<float>(slice_of<float>(c).cv, c.local_block);
     if (e != hipSuccess) return hip_fail(e, "local step attributes");
@@ -895,7 +923,7 @@ int autotune(npfem_batch_s* b, double h) {
     g.Npad = c.Npad;
     g.ncols = 3 * c.n_cells;
     g.mode = b->gemm_kind >= 2 ? EPI_SPLIT_SET : EPI_SET;
-    g.hm = h * h / c.mat.vertex_mass;
+    g.hm = c.hm_eff(h);
     g.beta = c.beta;
     float best = 1e30f;
     for (int tile = 0; tile < gemm_num_tiles(b->gemm_kind); ++tile) {
@@ -920,6 +948,7 @@ int autotune(npfem_batch_s* b, double h) {
     a.status = b->status;
     a.h = h;
     a.m = c.mat.vertex_mass;
+    a.mdelta = c.mat.vertex_mass * c.mass_scale(h) / (h * h);
     a.max_vol_iter = b->max_vol_iter;
     set_volume_tolerances(a, c, b->fp64);
     best = 1e30f;
@@ -1178,6 +1207,20 @@ int npfem_create_batch(const npfem_mesh* meshes, int32_t n_meshes, const int32_t
     c.vert0 = vert;
     c.local_block = default_local_block(c.N);
     c.gemm_tile = (3LL * n >= 1024) ? 3 : 0;
+    if (b->fp64 && n > 0) {
+      // the FP64 local step keeps q and the volume iterate as 32-byte
+      // records of N + 1 vertices each in LDS
+      ClassView<double> cv{};
+      cv.N = c.N;
+      cv.F = c.F;
+      cv.E = c.E;
+      const size_t need = local_smem_bytes<double>(cv, c.local_block);
+      if (need > 160 * 1024)
+        return fail(NPFEM_ERR_INVALID_ARG,
+                    "an FP64 batch takes meshes of at most 2550 vertices (the local step of a "
+                    "%d-vertex class needs %zu bytes of LDS, 163840 available)",
+                    c.N, need);
+    }
     col += 3LL * n;
     elem += 3LL * n * c.Npad;
     vert += (long long)n * c.N;
@@ -1288,6 +1331,39 @@ int npfem_set_weights(npfem_batch b, const double* cell_weights) {
   return rc;
 }
 
+int npfem_set_damping(npfem_batch b, int32_t cls, double alpha, double beta) {
+  g_err.clear();
+  if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
+  if (cls < -1 || cls >= (int)b->cls.size())
+    return fail(NPFEM_ERR_INVALID_ARG, "class index out of range");
+  if (!std::isfinite(alpha) || !std::isfinite(beta) || alpha < 0.0 || beta < 0.0)
+    return fail(NPFEM_ERR_INVALID_ARG, "damping coefficients must be finite and non-negative");
+  DeviceGuard guard(b->device);
+  HIP_TRY(hipStreamSynchronize(b->stream), "sync before damping update");
+  bool any_beta = false;
+  for (int k = 0; k < (int)b->cls.size(); ++k) {
+    if (cls < 0 || k == cls) {
+      b->cls[k].alpha = alpha;
+      b->cls[k].beta_d = beta;
+    }
+    any_beta = any_beta || b->cls[k].beta_d != 0.0;
+  }
+  if (any_beta && !b->damp) {
+    const size_t tsz = b->fp64 ? sizeof(double) : sizeof(float);
+    const int rc = dalloc(b, &b->damp, tsz * (size_t)b->total_elems, "damping buffer");
+    if (rc) return rc;
+    HIP_TRY(hipMemset(b->damp, 0, tsz * (size_t)b->total_elems), "memset");
+  }
+  // the operator depends on the damping: refactor and re-capture at the next step
+  b->dt = 0.0;
+  if (b->graph) {
+    hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  b->ro_valid = false;
+  return NPFEM_OK;
+}
+
 int npfem_rollout(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter,
                   int32_t n_steps, int32_t ckpt_every) {
   g_err.clear();
@@ -1332,6 +1408,9 @@ int npfem_rollout_adjoint(npfem_batch b, const void* dL_dx, const void* dL_dv, v
                 "no rollout to reverse (run npfem_rollout; weights and dt must not change)");
   if (b->gemm_kind == 3)
     return fail(NPFEM_ERR_INVALID_ARG, "the adjoint supports FP64, FP32 and BF16 batches");
+  for (const auto& c : b->cls)
+    if (c.alpha != 0.0 || c.beta_d != 0.0)
+      return fail(NPFEM_ERR_INVALID_ARG, "the adjoint does not cover viscous damping");
   DeviceGuard guard(b->device);
   HIP_TRY(hipStreamSynchronize(b->stream), "sync before adjoint");
   const int rc = b->fp64 ? adjoint_impl<double>(b, dL_dx, dL_dv, dL_dw, dL_df, dL_dx0, dL_dv0)

@@ -76,6 +76,7 @@ struct LocalArgs {
   float* colmax;       // [cols] max |r| per column (low-precision global step), or nullptr
   int* status;         // device flags
   double h, m;
+  double mdelta;       // coefficient of delta in r: m (1 + alpha h)/h^2 (m/h^2 undamped)
   int max_vol_iter;
   double vol_tol;      // relative settling test of the volume multiplier
   double vol_abs;      // absolute test: |d lam| |grad V|_2 below this (length units)
@@ -121,10 +122,12 @@ struct GemmArgs {
 enum StatusBits : int { ST_NONFINITE = 1 };
 
 // ---- launchers ----
+// alpha: mass-proportional damping coefficient (the first increment is
+// divided by 1 + alpha h); 0 without damping.
 template <typename T>
 hipError_t launch_predict(const ClassSlice<T>& cs, const T* pos, const T* vel, const T* force,
                           long long sumN, T* delta, T* cterm, int* status, double h,
-                          hipStream_t st);
+                          double alpha, hipStream_t st);
 template <typename T>
 hipError_t launch_update(const ClassSlice<T>& cs, T* pos, T* vel, long long sumN, const T* delta,
                          double h, hipStream_t st);
@@ -134,11 +137,15 @@ template <typename T>
 size_t local_smem_bytes(const ClassView<T>& cv, int block);
 template <typename T>
 hipError_t local_prepare(const ClassView<T>& cv, int block);
+// res = rhs - M (delta - delta0) with M = (cm m + cv w_v) I + cl ((w_s + w_a)
+// L_tri + w_b L_bend) per cell (w the cell's weights, m the class mass).
+// The system matrix: cm = 1/h^2, cl = cv = 1; with damping cm = (1 + alpha
+// h)/h^2, cl = 1 + beta/h.
 template <typename T>
 hipError_t launch_residual(const ClassSlice<T>& cs, const T* rhs, const T* delta,
                            const T* delta0, T* res, const T* weights, float* colmax,
-                           const float* need, double need_factor, double need_thr, double h,
-                           hipStream_t st);
+                           const float* need, double need_factor, double need_thr, double cm,
+                           double cl, double cv, hipStream_t st);
 // Cells the static staging buffer of npfem_get_volume_noalloc holds, and the
 // devices whose addresses of it are kept.
 constexpr int kVolumeScratchCells = 1 << 16;

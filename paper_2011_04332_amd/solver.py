@@ -143,6 +143,10 @@ class Batch:
             raise ValueError("cell_weights must be [n_cells, 4]")
         _lib.check(_lib.load().npfem_set_weights(self.handle, None if w is None else w.ctypes.data))
 
+    def set_damping(self, cls: int, alpha: float, beta: float):
+        """Viscous damping C = alpha m I + beta K_d of class cls (-1: all)."""
+        _lib.check(_lib.load().npfem_set_damping(self.handle, int(cls), float(alpha), float(beta)))
+
     def rollout(self, forces: torch.Tensor, dt: float, n_iter: int, n_steps: int, ckpt_every: int):
         """n_steps steps under constant forces, checkpointing every ckpt_every steps."""
         self._check_field(forces, "forces")
@@ -234,4 +238,8 @@ def batch_from_suspension(susp, precision="fp32", device="cuda", per_cell_weight
         per_cell_weights = not susp.uniform_weights()
     w = susp.weights if per_cell_weights else None
     b = Batch(meshes, susp.cell_class, pos, vel, cell_weights=w, precision=precision, **kw)
+    for k, c in enumerate(susp.classes):
+        alpha, beta = getattr(c, "damping", (0.0, 0.0))
+        if alpha or beta:
+            b.set_damping(k, alpha, beta)
     return b, pos, vel, f, meshes

@@ -179,7 +179,8 @@ def test_full_size_lattice_stiff_bench_kernel(prec, cfg):
 def test_volume_and_energy_reductions(prec):
     """Per-cell FP64 reductions against the oracle, cell by cell, on the
     lattice and the uneven batch (stiff twins, so that the energy's elastic
-    terms are not negligible):
+    terms are not negligible; FP64 without the large class, see
+    test_fp64_refuses_meshes_beyond_lds):
     * npfem_get_volume of the positions the GPU holds equals the oracle's
       volume formula on the same positions (1e-13 relative: FP64 sums of the
       same products), and follows the oracle's trajectory (volume of the
@@ -195,9 +196,12 @@ def test_volume_and_energy_reductions(prec):
         if wl == "lattice":
             s = W.stiff(W.rbc_lattice(n_cells=16, n_steps=2))
             cells = [0, 7, 15]
-        else:
+        elif prec == "fp32":
             s = W.stiff(W.uneven(n_rbc=6, n_plt=4, n_large=2, n_steps=2))
             cells = [0, 6, 9, 10, 11]
+        else:  # (FP64 batches take meshes of at most 2550 vertices)
+            s = W.stiff(W.uneven(n_rbc=6, n_plt=4, n_large=0, n_steps=2))
+            cells = [0, 6, 9]
         if prec == "fp32":
             s = as_precision(s, np.float32)
         n_iter = 4
@@ -248,3 +252,13 @@ def test_uneven_batch_full_size(stiff):
     err = max_error(s, x, oracle_cells(s, cells))
     log(f"uneven full size stiff={stiff} err {err:.3e}")
     assert err <= TOL["fp32"]
+
+
+def test_fp64_refuses_meshes_beyond_lds():
+    """An FP64 batch with the 2562-vertex class is refused at creation with a
+    clear error (its local step would need more than 160 KB of LDS)."""
+    from paper_2011_04332_amd import _lib, solver
+    s = W.uneven(n_rbc=1, n_plt=1, n_large=1, n_steps=1)
+    with pytest.raises(_lib.NpfemError) as e:
+        solver.batch_from_suspension(s, precision="fp64")
+    assert e.value.code == _lib.ERR_INVALID_ARG and "2550" in str(e.value)
