@@ -191,6 +191,61 @@ int npfem_set_weights(npfem_batch b, const double* cell_weights);
  * negative or non-finite coefficients), HIP, OOM. */
 int npfem_set_damping(npfem_batch b, int32_t cls, double alpha, double beta);
 
+/* Contact (collision) potentials of every cell against its colliding
+ * neighbours, which the caller supplies (the fluid side exchanges them,
+ * Implementation and architecture; their strength is the collision weight,
+ * section "RBC collision at an obstacle"). Cell c's neighbourhood is the list
+ * of contact points y_k, k in [cell_offsets[c], cell_offsets[c + 1]), on
+ * the other surfaces (neighbouring cells, obstacles), each with the unit
+ * outward normal n_k of that surface, in c's cell-local coordinates. Every
+ * vertex carries the potential (weight/2) dist^2(q_v, C_v), C_v the
+ * half-space (p - y_k) . n_k >= 0 of the contact point nearest to q_v
+ * (first on ties): vertices outside it feel nothing, vertices inside are
+ * pulled to its tangent plane. Since every vertex carries it, the system
+ * matrix gains weight * I and stays constant.
+ *   weight        > 0 enables, 0 disables (the arrays may then be NULL)
+ *   points, normals  device SoA [3][n_points], element type as pos
+ *   cell_offsets  device int32 [n_cells + 1], non-decreasing
+ * The arrays are caller-owned and read at every step: their contents may
+ * change between steps (move the contacts), their addresses may not without
+ * a new call. A changed weight refactors at the next step; any call
+ * re-captures. Each vertex scans its cell's list (cost ~ points per cell).
+ * npfem_rollout_adjoint does not cover contacts (INVALID_ARG). Synchronises.
+ * Errors: INVALID_ARG (negative or non-finite weight, NULL arrays with a
+ * positive weight), HIP. */
+int npfem_set_contacts(npfem_batch b, double weight, const void* points, const void* normals,
+                       const int32_t* cell_offsets, int64_t n_points);
+
+/* Immersed-boundary transfer between a periodic Cartesian fluid grid and the
+ * vertices (the coupling on either side of the solid step: the IBM computes
+ * the body force of eqs. 1 and 2, and the data exchange between the grid and
+ * the surface meshes goes through interpolation kernels, Introduction), with
+ * Peskin's 4-point regularised delta function
+ *   delta_h(x) = phi(x/dx) phi(y/dx) phi(z/dx) / dx^3,
+ *   phi(r) = (3 - 2|r| + sqrt(1 + 4|r| - 4r^2))/8       for |r| <= 1,
+ *            (5 - 2|r| - sqrt(-7 + 12|r| - 4r^2))/8      for 1 <= |r| <= 2.
+ * Grid node (i, j, k) sits at grid_origin + dx (i, j, k) (host [3]); indices
+ * wrap periodically over dims (host [3], each >= 4). Grid fields are device
+ * SoA [3][nx ny nz], flat index i + nx (j + ny k), element type as pos. A
+ * vertex's global position is cell_origins[c] (device FP64 [n_cells][3]) plus
+ * its cell-local position (the batch's current pos).
+ * npfem_ibm_interpolate: out_u (device SoA [3][sum_N]) = sum over the 64 nodes
+ *   around each vertex of u_g phi phi phi (the fluid velocity at the vertex).
+ * npfem_ibm_spread: grid_f = sum_v F_v delta_h(x_g - X_v) (a force density;
+ *   sum_g grid_f dx^3 = sum_v F_v), bitwise reproducible: contributions are
+ *   added as 64-bit fixed-point integers scaled from max |F| (~40 bits below
+ *   the largest possible contribution), then converted. The first call for a
+ *   grid larger than any before allocates the accumulators (3 x 8 bytes per
+ *   node); otherwise nothing is allocated. Non-finite forces set the flag of
+ *   npfem_sync_status.
+ * Both enqueue on the batch stream and return without synchronising. Errors:
+ * INVALID_ARG (NULL arrays, dims < 4 or > 2e9 nodes, dx <= 0), HIP, OOM. */
+int npfem_ibm_interpolate(npfem_batch b, const double* cell_origins, const void* grid_u,
+                          const int32_t dims[3], double dx, const double grid_origin[3],
+                          void* out_u);
+int npfem_ibm_spread(npfem_batch b, const double* cell_origins, const void* vertex_f,
+                     const int32_t dims[3], double dx, const double grid_origin[3], void* grid_f);
+
 /* Differentiable rollout: n_steps calls of npfem_step under constant forces,
  * storing (positions, velocities) before every ckpt_every-th step as
  * checkpoints for npfem_rollout_adjoint (the time-step loop the adjoint

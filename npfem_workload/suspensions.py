@@ -240,3 +240,44 @@ def sample_cells(s: Suspension, n_per_class, seed=0):
             continue
         out.append(np.sort(rng.choice(ids, size=min(n, len(ids)), replace=False)))
     return np.concatenate(out) if out else np.zeros(0, dtype=np.int64)
+
+
+def wall_contacts(s: Suspension, depth=0.3, n_grid=9, weight=10.0) -> Suspension:
+    """Contact lists of a plane wall under every cell (an obstacle, as in the
+    single-RBC obstacle case): the wall's surface cuts `depth` um above the
+    cell's lowest vertex; contact points on an n_grid x n_grid grid over the
+    cell's footprint, outward normals +z (out of the wall), cell-local
+    coordinates. Sets extra['contacts'] = (points [P,3], normals [P,3],
+    offsets [C+1]) and extra['contact_weight']."""
+    pts, nrm, off = [], [], [0]
+    for c in range(s.n_cells):
+        x = s.x0[:, s.cell_slice(c)].T
+        zmin = x[:, 2].min()
+        r = np.abs(x[:, :2]).max()
+        g = np.linspace(-r, r, n_grid)
+        p2 = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+        pts.append(np.c_[p2, np.full(len(p2), zmin + depth)])
+        nrm.append(np.tile([0.0, 0.0, 1.0], (len(p2), 1)))
+        off.append(off[-1] + len(p2))
+    s.extra["contacts"] = (np.concatenate(pts), np.concatenate(nrm), np.asarray(off, np.int64))
+    s.extra["contact_weight"] = float(weight)
+    return s
+
+
+def sphere_contacts(s: Suspension, radius=2.0, overlap=0.3, level=2, weight=10.0) -> Suspension:
+    """Contact lists of a spherical obstacle beside every cell: centre on the
+    cell's +x side so that the sphere reaches `overlap` um into the cell's
+    extent along x; contact points are the vertices of an icosphere of that
+    radius with their radial (outward) normals, cell-local coordinates."""
+    u, _ = meshes.icosphere(level)
+    u = u / np.linalg.norm(u, axis=1, keepdims=True)
+    pts, nrm, off = [], [], [0]
+    for c in range(s.n_cells):
+        x = s.x0[:, s.cell_slice(c)].T
+        ctr = np.array([x[:, 0].max() + radius - overlap, x[:, 1].mean(), x[:, 2].mean()])
+        pts.append(ctr + radius * u)
+        nrm.append(u.copy())
+        off.append(off[-1] + len(u))
+    s.extra["contacts"] = (np.concatenate(pts), np.concatenate(nrm), np.asarray(off, np.int64))
+    s.extra["contact_weight"] = float(weight)
+    return s

@@ -27,6 +27,7 @@ from dataclasses import dataclass
 import numpy as np
 import scipy.linalg
 
+from . import contacts as contacts_mod
 from . import operators as ops_mod
 from . import projections as proj
 
@@ -98,10 +99,14 @@ class CellSolver:
     q^0 = (s + alpha h x_n)/(1 + alpha h) (s itself without damping), which
     keeps the momentum balance exact at every iteration count."""
 
-    def __init__(self, o: ops_mod.CellOperators, prm: Params):
+    def __init__(self, o: ops_mod.CellOperators, prm: Params, contact_weight: float = 0.0):
         self.o = o
         self.prm = prm
+        self.wc = float(contact_weight)
         self.A = ops_mod.system_matrix(o, prm.weights, prm.mass, prm.dt)
+        if self.wc != 0.0:
+            # every vertex carries the contact potential (oracle.contacts)
+            self.A = self.A + self.wc * np.eye(o.n_verts)
         alpha, beta = prm.damping
         self.C = None
         if alpha != 0.0 or beta != 0.0:
@@ -109,35 +114,49 @@ class CellSolver:
             self.A = self.A + self.C / prm.dt
         self.chol = ops_mod.factor(self.A)
 
-    def step(self, x, v, f, n_iter, record_energy=False):
+    def step(self, x, v, f, n_iter, record_energy=False, contacts=None):
         """One time step; returns (x_new, v_new, energies) with energies
         E(q^0..q^n_iter) when requested. Readings: a fixed count of n_iter
         local/global iterations from q^0 = s (the inertial prediction),
-        v = (q - x) / h, no damping."""
+        v = (q - x) / h, no damping. contacts = (points [K,3], normals [K,3])
+        of the cell's neighbourhood (oracle.contacts), with the weight given
+        at construction."""
         h, m = self.prm.dt, self.prm.mass
         s = x + h * v + (h * h / m) * f
         alpha = self.prm.damping[0]
         q = s.copy() if alpha == 0.0 else (s + alpha * h * x) / (1.0 + alpha * h)
         energies = []
         cx = None if self.C is None else (self.C @ x) / h
+        use_c = contacts is not None and self.wc != 0.0
         for _ in range(n_iter):
             P = proj.local_step(q, self.o)
+            if use_c:
+                Pc = contacts_mod.project_contacts(q, contacts[0], contacts[1])
             if record_energy:
-                energies.append(energy(self.o, q, s, P, self.prm, x, self.C))
+                e = energy(self.o, q, s, P, self.prm, x, self.C)
+                if use_c:
+                    e += 0.5 * self.wc * float(np.sum((q - Pc) ** 2))
+                energies.append(e)
             b = rhs(self.o, P, s, self.prm)
             if cx is not None:
                 b = b + cx
+            if use_c:
+                b = b + self.wc * Pc
             q = scipy.linalg.cho_solve(self.chol, b)
         if record_energy:
             P = proj.local_step(q, self.o)
-            energies.append(energy(self.o, q, s, P, self.prm, x, self.C))
+            e = energy(self.o, q, s, P, self.prm, x, self.C)
+            if use_c:
+                Pc = contacts_mod.project_contacts(q, contacts[0], contacts[1])
+                e += 0.5 * self.wc * float(np.sum((q - Pc) ** 2))
+            energies.append(e)
         return q, (q - x) / h, energies
 
-    def rollout(self, x0, v0, f, n_iter, n_steps, forces_per_step=None):
+    def rollout(self, x0, v0, f, n_iter, n_steps, forces_per_step=None, contacts=None):
         x, v = x0.copy(), v0.copy()
         for n in range(n_steps):
             fn = f if forces_per_step is None else forces_per_step[n]
-            x, v, _ = self.step(x, v, fn, n_iter)
+            x, v, _ = self.step(x, v, fn, n_iter, contacts=contacts)
         return x, v
 
 
@@ -153,15 +172,26 @@ def operators_for(mesh_class) -> ops_mod.CellOperators:
     return o
 
 
+def cell_contacts(susp, c: int):
+    """(contact weight, (points, normals) or None) of cell c of a suspension."""
+    wc = float(susp.extra.get("contact_weight", 0.0))
+    ct = susp.extra.get("contacts")
+    if ct is None or wc == 0.0:
+        return wc, None
+    pts, nrm, off = ct
+    return wc, (pts[off[c]:off[c + 1]], nrm[off[c]:off[c + 1]])
+
+
 def run_cell(susp, c: int, n_steps=None, n_iter=None, dt=None):
     """Roll out one cell of a suspension; returns (x [N,3], v [N,3]) local coords."""
     mc, x0, v0, f, w = susp.cell_arrays(c)
     o = operators_for(mc)
     prm = Params(tuple(w), mc.mass, susp.dt if dt is None else dt,
                  tuple(getattr(mc, "damping", (0.0, 0.0))))
-    solver = CellSolver(o, prm)
+    wc, ct = cell_contacts(susp, c)
+    solver = CellSolver(o, prm, wc)
     return solver.rollout(x0, v0, f, susp.n_iter if n_iter is None else n_iter,
-                          susp.n_steps if n_steps is None else n_steps)
+                          susp.n_steps if n_steps is None else n_steps, contacts=ct)
 
 
 def run_cells(susp, cells, n_steps=None, n_iter=None):

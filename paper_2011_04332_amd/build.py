@@ -27,6 +27,7 @@ SOURCES = [
     "kernels_gemm.hip",
     "kernels_factor.hip",
     "kernels_adjoint.hip",
+    "kernels_ibm.hip",
 ]
 
 # Packed-FP32 VALU instructions are kept out of all device code: the compiler

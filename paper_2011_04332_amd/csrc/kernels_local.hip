@@ -299,6 +299,45 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
     }
   }
 
+  // ---- contacts: w_c (Pc - q) with Pc the closest point of q in the
+  // half-space of its nearest contact point (first minimum on ties) ----
+  if (a.contact_w != 0.0) {  // (uniform)
+    const int k0 = a.contact_off[cell], k1 = a.contact_off[cell + 1];
+    const T* __restrict__ cpx = a.contact_p;
+    const T* __restrict__ cpy = cpx + a.contact_np;
+    const T* __restrict__ cpz = cpy + a.contact_np;
+    const T* __restrict__ cnx = a.contact_n;
+    const T* __restrict__ cny = cnx + a.contact_np;
+    const T* __restrict__ cnz = cny + a.contact_np;
+    const T wc = T(a.contact_w);
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const int v = tid + j * BLOCK;
+      if (v < N && k1 > k0) {
+        const V4<T> q = qs[v];
+        T best = T(0);
+        int kb = k0;
+        for (int k = k0; k < k1; ++k) {
+          const T dx = q.x - cpx[k], dy = q.y - cpy[k], dz = q.z - cpz[k];
+          const T d2 = dx * dx + dy * dy + dz * dz;
+          if (k == k0 || d2 < best) {
+            best = d2;
+            kb = k;
+          }
+        }
+        const T nx = cnx[kb], ny = cny[kb], nz = cnz[kb];
+        const T sd = (q.x - cpx[kb]) * nx + (q.y - cpy[kb]) * ny + (q.z - cpz[kb]) * nz;
+        if (sd < T(0)) {
+          const T f = -wc * sd;
+          acc[j][0] += f * nx;
+          acc[j][1] += f * ny;
+          acc[j][2] += f * nz;
+          if (want_energy) e_acc += 0.5 * (double)wc * (double)sd * (double)sd;
+        }
+      }
+    }
+  }
+
   // inertia term of the own vertices, cterm - (m/h^2) delta, loaded here so
   // that the loads are in flight during the hinge phase (barriers wait for
   // LDS only)

@@ -87,11 +87,16 @@ struct ClassState {
   // viscous damping C = alpha m I + beta ((w_s + w_a) L_tri + w_b L_bend)
   // (npfem_set_damping); 0, 0 = none
   double alpha = 0.0, beta_d = 0.0;
+  // contact weight of the batch (npfem_set_contacts): w_c I in the system
+  double wc = 0.0;
   // the damped system A + C/h is the undamped one with the mass and the
-  // stretch/area/bend weights scaled: these are the scales at time step h
+  // stretch/area/bend weights scaled: these are the scales at time step h;
+  // the contact potentials add w_c to the diagonal, which the operator sees
+  // as the mass diag_mass(h) = m (1 + alpha h) + w_c h^2
   double mass_scale(double h) const { return 1.0 + alpha * h; }
   double lap_scale(double h) const { return 1.0 + beta_d / h; }
-  double hm_eff(double h) const { return h * h / (mat.vertex_mass * mass_scale(h)); }
+  double diag_mass(double h) const { return mat.vertex_mass * mass_scale(h) + wc * h * h; }
+  double hm_eff(double h) const { return h * h / diag_mass(h); }
 };
 
 }  // namespace
@@ -122,6 +127,15 @@ struct npfem_batch_s {
   void* rhs = nullptr;
   void* res = nullptr;
   void* damp = nullptr;         // right-hand side with the stiffness damping term (columns)
+  // immersed-boundary spreading: 64-bit fixed-point accumulators [3][nodes]
+  // and the max |F| word in front of them
+  unsigned long long* ibm_acc = nullptr;
+  long long ibm_cap = 0;  // nodes the accumulators hold
+  // contact data (caller-owned device arrays, npfem_set_contacts)
+  const void* ct_points = nullptr;
+  const void* ct_normals = nullptr;
+  const int* ct_off = nullptr;
+  long long ct_np = 0;
   float* colmax = nullptr;      // max |r| per column (16-bit products)
   float* colmax_res = nullptr;  // max |res| per column of the correction sweeps
   int* status = nullptr;
@@ -493,7 +507,7 @@ int choose_refine(npfem_batch_s* b, double dt, int* out) {
   if (b->per_cell) {
     for (const ClassState& c : b->cls) {
       const double w0[4] = {c.mat.w_stretch, c.mat.w_area, c.mat.w_bend, c.mat.w_volume};
-      const double lmin = c.mat.vertex_mass * c.mass_scale(dt) / (dt * dt) + c.mat.w_volume;
+      const double lmin = c.diag_mass(dt) / (dt * dt) + c.mat.w_volume;
       const double ls = c.lap_scale(dt);
       for (int i = 0; i < c.n_cells; ++i) {
         const double* w = &b->weights_host[4 * (size_t)(c.cell0 + i)];
@@ -590,7 +604,7 @@ int factorise(npfem_batch_s* b, double dt) {
     const double ls = c.lap_scale(dt);
     const double w0[4] = {ls * c.mat.w_stretch, ls * c.mat.w_area, ls * c.mat.w_bend,
                           c.mat.w_volume};
-    dense_system_matrix(c.ops, w0, c.mat.vertex_mass * c.mass_scale(dt), dt, hA.data(), c.Npad);
+    dense_system_matrix(c.ops, w0, c.diag_mass(dt), dt, hA.data(), c.Npad);
     int hfail = 0;
     e = hipMemcpy(dA, hA.data(), sizeof(double) * hA.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(dfail, 0, sizeof(int));
@@ -714,8 +728,9 @@ int enqueue_solve(npfem_batch_s* b, ClassState& c, T* B, T* C, const T* D, doubl
                 launch_residual<T>(slice_of<T>(c), B, C, D, res, w,
                                    (lp || adapt) ? b->colmax_res : nullptr,
                                    adapt ? b->colmax : nullptr, bound,
-                                   std::ldexp(1.0, -24) * c.r_rest, c.mass_scale(h) / (h * h),
-                                   c.lap_scale(h), 1.0, st),
+                                   std::ldexp(1.0, -24) * c.r_rest,
+                                   c.diag_mass(h) / (h * h * c.mat.vertex_mass), c.lap_scale(h),
+                                   1.0, st),
                 "residual");
     GemmArgs r = g;
     r.B = res + c.elem0;
@@ -767,6 +782,13 @@ int enqueue_class_step(npfem_batch_s* b, ClassState& c, T* pos, T* vel, const T*
     a.h = h;
     a.m = c.mat.vertex_mass;
     a.mdelta = c.mat.vertex_mass * c.mass_scale(h) / (h * h);
+    if (c.wc != 0.0) {
+      a.contact_w = c.wc;
+      a.contact_p = static_cast<const T*>(b->ct_points);
+      a.contact_n = static_cast<const T*>(b->ct_normals);
+      a.contact_off = b->ct_off;
+      a.contact_np = b->ct_np;
+    }
     a.max_vol_iter = b->max_vol_iter;
     set_volume_tolerances(a, c, b->fp64);
     NPFEM_TIMED(NPFEM_KERNEL_LOCAL, launch_local<T>(a, c.local_block, st), "local step");
@@ -1364,6 +1386,126 @@ int npfem_set_damping(npfem_batch b, int32_t cls, double alpha, double beta) {
   return NPFEM_OK;
 }
 
+int npfem_set_contacts(npfem_batch b, double weight, const void* points, const void* normals,
+                       const int32_t* cell_offsets, int64_t n_points) {
+  g_err.clear();
+  if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
+  if (!std::isfinite(weight) || weight < 0.0)
+    return fail(NPFEM_ERR_INVALID_ARG, "contact weight must be finite and non-negative");
+  if (weight > 0.0 && (!points || !normals || !cell_offsets || n_points < 0))
+    return fail(NPFEM_ERR_INVALID_ARG, "contact arrays are NULL or n_points < 0");
+  DeviceGuard guard(b->device);
+  HIP_TRY(hipStreamSynchronize(b->stream), "sync before contact update");
+  bool refactor = false;
+  for (auto& c : b->cls) {
+    refactor = refactor || c.wc != weight;
+    c.wc = weight;
+  }
+  b->ct_points = weight > 0.0 ? points : nullptr;
+  b->ct_normals = weight > 0.0 ? normals : nullptr;
+  b->ct_off = weight > 0.0 ? cell_offsets : nullptr;
+  b->ct_np = weight > 0.0 ? n_points : 0;
+  // the weight is in the operator (refactor); the arrays' addresses are in
+  // the captured graph (re-capture)
+  if (refactor) b->dt = 0.0;
+  if (b->graph) {
+    hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  b->ro_valid = false;
+  return NPFEM_OK;
+}
+
+static int ibm_grid(const int32_t dims[3], double dx, const double origin[3], IbmGrid* g) {
+  if (!dims || !origin) return fail(NPFEM_ERR_INVALID_ARG, "grid dims or origin is NULL");
+  if (dims[0] < 4 || dims[1] < 4 || dims[2] < 4)
+    return fail(NPFEM_ERR_INVALID_ARG, "grid must have at least 4 nodes per axis");
+  if ((double)dims[0] * dims[1] * dims[2] > 2.0e9)
+    return fail(NPFEM_ERR_INVALID_ARG, "grid too large (more than 2e9 nodes)");
+  if (!(dx > 0.0) || !std::isfinite(dx) || !std::isfinite(origin[0]) ||
+      !std::isfinite(origin[1]) || !std::isfinite(origin[2]))
+    return fail(NPFEM_ERR_INVALID_ARG, "dx must be finite and > 0, the origin finite");
+  *g = IbmGrid{dims[0], dims[1], dims[2], dx, origin[0], origin[1], origin[2]};
+  return NPFEM_OK;
+}
+
+int npfem_ibm_interpolate(npfem_batch b, const double* cell_origins, const void* grid_u,
+                          const int32_t dims[3], double dx, const double grid_origin[3],
+                          void* out_u) {
+  g_err.clear();
+  if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
+  if (!cell_origins || !grid_u || !out_u) return fail(NPFEM_ERR_INVALID_ARG, "NULL array");
+  IbmGrid g;
+  int rc = ibm_grid(dims, dx, grid_origin, &g);
+  if (rc) return rc;
+  DeviceGuard guard(b->device);
+  for (auto& c : b->cls) {
+    hipError_t e =
+        b->fp64 ? launch_ibm_interpolate<double>(slice_of<double>(c), (const double*)b->pos,
+                                                 b->sumN, cell_origins, (const double*)grid_u, g,
+                                                 (double*)out_u, b->stream)
+                : launch_ibm_interpolate<float>(slice_of<float>(c), (const float*)b->pos,
+                                                b->sumN, cell_origins, (const float*)grid_u, g,
+                                                (float*)out_u, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "IBM interpolation");
+  }
+  return NPFEM_OK;
+}
+
+int npfem_ibm_spread(npfem_batch b, const double* cell_origins, const void* vertex_f,
+                     const int32_t dims[3], double dx, const double grid_origin[3], void* grid_f) {
+  g_err.clear();
+  if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
+  if (!cell_origins || !vertex_f || !grid_f) return fail(NPFEM_ERR_INVALID_ARG, "NULL array");
+  IbmGrid g;
+  int rc = ibm_grid(dims, dx, grid_origin, &g);
+  if (rc) return rc;
+  DeviceGuard guard(b->device);
+  const long long nodes = (long long)g.nx * g.ny * g.nz;
+  if (nodes > b->ibm_cap) {
+    HIP_TRY(hipStreamSynchronize(b->stream), "sync before IBM accumulators");
+    if (b->ibm_acc) {
+      auto it = std::find(b->allocs.begin(), b->allocs.end(), (void*)b->ibm_acc);
+      if (it != b->allocs.end()) b->allocs.erase(it);
+      hipFree(b->ibm_acc);
+      b->ibm_acc = nullptr;
+      b->ibm_cap = 0;
+    }
+    void* p = nullptr;
+    if ((rc = dalloc(b, &p, sizeof(unsigned long long) * (size_t)(3 * nodes + 32), "IBM accumulators")))
+      return rc;
+    b->ibm_acc = static_cast<unsigned long long*>(p);
+    b->ibm_cap = nodes;
+  }
+  unsigned long long* mx = b->ibm_acc;         // max |F| word (own 256-byte line)
+  unsigned long long* acc = b->ibm_acc + 32;   // [3][nodes]
+  HIP_TRY(launch_ibm_zero(b->ibm_acc, 3 * nodes + 32, b->stream), "IBM accumulators");
+  const double n_total = (double)b->sumN;
+  for (auto& c : b->cls) {
+    hipError_t e = b->fp64 ? launch_ibm_maxabs<double>(slice_of<double>(c), (const double*)vertex_f,
+                                                       b->sumN, mx, b->status, b->stream)
+                           : launch_ibm_maxabs<float>(slice_of<float>(c), (const float*)vertex_f,
+                                                      b->sumN, mx, b->status, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "IBM force scale");
+  }
+  for (auto& c : b->cls) {
+    hipError_t e =
+        b->fp64 ? launch_ibm_spread<double>(slice_of<double>(c), (const double*)b->pos, b->sumN,
+                                            cell_origins, (const double*)vertex_f, g, mx, n_total,
+                                            acc, b->stream)
+                : launch_ibm_spread<float>(slice_of<float>(c), (const float*)b->pos, b->sumN,
+                                           cell_origins, (const float*)vertex_f, g, mx, n_total,
+                                           acc, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "IBM spreading");
+  }
+  hipError_t e = b->fp64 ? launch_ibm_convert<double>(acc, 3 * nodes, mx, n_total, dx,
+                                                      (double*)grid_f, b->stream)
+                         : launch_ibm_convert<float>(acc, 3 * nodes, mx, n_total, dx,
+                                                     (float*)grid_f, b->stream);
+  if (e != hipSuccess) return hip_fail(e, "IBM conversion");
+  return NPFEM_OK;
+}
+
 int npfem_rollout(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter,
                   int32_t n_steps, int32_t ckpt_every) {
   g_err.clear();
@@ -1409,8 +1551,9 @@ int npfem_rollout_adjoint(npfem_batch b, const void* dL_dx, const void* dL_dv, v
   if (b->gemm_kind == 3)
     return fail(NPFEM_ERR_INVALID_ARG, "the adjoint supports FP64, FP32 and BF16 batches");
   for (const auto& c : b->cls)
-    if (c.alpha != 0.0 || c.beta_d != 0.0)
-      return fail(NPFEM_ERR_INVALID_ARG, "the adjoint does not cover viscous damping");
+    if (c.alpha != 0.0 || c.beta_d != 0.0 || c.wc != 0.0)
+      return fail(NPFEM_ERR_INVALID_ARG,
+                  "the adjoint does not cover viscous damping or contact potentials");
   DeviceGuard guard(b->device);
   HIP_TRY(hipStreamSynchronize(b->stream), "sync before adjoint");
   const int rc = b->fp64 ? adjoint_impl<double>(b, dL_dx, dL_dv, dL_dw, dL_df, dL_dx0, dL_dv0)

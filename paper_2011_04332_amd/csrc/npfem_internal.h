@@ -77,6 +77,13 @@ struct LocalArgs {
   int* status;         // device flags
   double h, m;
   double mdelta;       // coefficient of delta in r: m (1 + alpha h)/h^2 (m/h^2 undamped)
+  // contact potentials (0 weight: none): points and outward normals SoA
+  // [3][n_points] in cell-local coordinates, cell c's at [off[c], off[c + 1])
+  double contact_w = 0.0;
+  const T* contact_p = nullptr;
+  const T* contact_n = nullptr;
+  const int* contact_off = nullptr;
+  long long contact_np = 0;
   int max_vol_iter;
   double vol_tol;      // relative settling test of the volume multiplier
   double vol_abs;      // absolute test: |d lam| |grad V|_2 below this (length units)
@@ -158,6 +165,30 @@ template <typename T>
 hipError_t launch_volume(const ClassSlice<T>& cs, const T* pos, long long sumN, double* out,
                          hipStream_t st);
 
+// Periodic Cartesian fluid grid of the immersed-boundary transfer
+// (kernels_ibm.hip): node (i, j, k) at (ox, oy, oz) + dx (i, j, k), fields
+// SoA [3][nx ny nz] with flat index i + nx (j + ny k).
+struct IbmGrid {
+  int nx, ny, nz;
+  double dx, ox, oy, oz;
+};
+template <typename T>
+hipError_t launch_ibm_interpolate(const ClassSlice<T>& cs, const T* pos, long long sumN,
+                                  const double* origins, const T* u, const IbmGrid& g, T* out,
+                                  hipStream_t st);
+template <typename T>
+hipError_t launch_ibm_maxabs(const ClassSlice<T>& cs, const T* f, long long sumN,
+                             unsigned long long* mx, int* status, hipStream_t st);
+template <typename T>
+hipError_t launch_ibm_spread(const ClassSlice<T>& cs, const T* pos, long long sumN,
+                             const double* origins, const T* f, const IbmGrid& g,
+                             const unsigned long long* mx, double n_total,
+                             unsigned long long* acc, hipStream_t st);
+template <typename T>
+hipError_t launch_ibm_convert(const unsigned long long* acc, long long count,
+                              const unsigned long long* mx, double n_total, double dx, T* out,
+                              hipStream_t st);
+hipError_t launch_ibm_zero(unsigned long long* p, long long count, hipStream_t st);
 template <typename T>
 hipError_t adjoint_prepare(const ClassView<T>& cv);
 template <typename T>

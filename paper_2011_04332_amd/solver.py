@@ -147,6 +147,68 @@ class Batch:
         """Viscous damping C = alpha m I + beta K_d of class cls (-1: all)."""
         _lib.check(_lib.load().npfem_set_damping(self.handle, int(cls), float(alpha), float(beta)))
 
+    def set_contacts(self, weight: float, points=None, normals=None, cell_offsets=None):
+        """Contact potentials: points / normals device SoA [3][P] (pos dtype),
+        cell_offsets device int32 [n_cells + 1]; weight 0 disables. The
+        tensors must stay alive (and at their addresses) while stepping."""
+        if weight and not (points is not None and normals is not None and cell_offsets is not None):
+            raise ValueError("contact arrays are required with a positive weight")
+        if weight:
+            for t, name in ((points, "points"), (normals, "normals")):
+                if not (t.is_cuda and t.dtype == self.dtype and t.is_contiguous() and t.dim() == 2
+                        and t.shape[0] == 3):
+                    raise ValueError(f"{name} must be a contiguous CUDA [3, P] tensor of the state dtype")
+            if not (cell_offsets.is_cuda and cell_offsets.dtype == torch.int32
+                    and tuple(cell_offsets.shape) == (self.n_cells + 1,)):
+                raise ValueError("cell_offsets must be a CUDA int32 tensor [n_cells + 1]")
+            self._contacts = (points, normals, cell_offsets)
+            np_ = points.shape[1]
+            _lib.check(_lib.load().npfem_set_contacts(self.handle, float(weight), points.data_ptr(),
+                                                      normals.data_ptr(), cell_offsets.data_ptr(),
+                                                      int(np_)))
+        else:
+            self._contacts = None
+            _lib.check(_lib.load().npfem_set_contacts(self.handle, 0.0, None, None, None, 0))
+
+    def _grid_args(self, grid, dims, origin):
+        dims = np.ascontiguousarray(dims, dtype=np.int32)
+        origin = np.ascontiguousarray(origin, dtype=np.float64)
+        if dims.shape != (3,) or origin.shape != (3,):
+            raise ValueError("dims and origin must have 3 entries")
+        n = int(np.prod(dims.astype(np.int64)))
+        if not (grid.is_cuda and grid.dtype == self.dtype and grid.is_contiguous()
+                and tuple(grid.shape) == (3, n)):
+            raise ValueError("grid field must be a contiguous CUDA [3, nx*ny*nz] tensor of the state dtype")
+        return dims, origin
+
+    def _origins(self, cell_origins):
+        if not (cell_origins.is_cuda and cell_origins.dtype == torch.float64
+                and cell_origins.is_contiguous() and tuple(cell_origins.shape) == (self.n_cells, 3)):
+            raise ValueError("cell_origins must be a contiguous CUDA float64 [n_cells, 3] tensor")
+
+    def ibm_interpolate(self, cell_origins, grid_u, dims, dx, origin, out=None):
+        """Fluid velocity at the vertices (Peskin 4-point kernel, periodic grid)."""
+        self._origins(cell_origins)
+        dims, origin = self._grid_args(grid_u, dims, origin)
+        out = torch.empty_like(self.pos) if out is None else out
+        self._check_field(out, "out")
+        _lib.check(_lib.load().npfem_ibm_interpolate(self.handle, cell_origins.data_ptr(),
+                                                     grid_u.data_ptr(), dims.ctypes.data, float(dx),
+                                                     origin.ctypes.data, out.data_ptr()))
+        return out
+
+    def ibm_spread(self, cell_origins, vertex_f, dims, dx, origin, out=None):
+        """Force density on the grid from the vertex forces (bitwise reproducible)."""
+        self._origins(cell_origins)
+        self._check_field(vertex_f, "vertex_f")
+        n = int(np.prod(np.asarray(dims, dtype=np.int64)))
+        out = torch.empty((3, n), dtype=self.dtype, device=self.pos.device) if out is None else out
+        dims, origin = self._grid_args(out, dims, origin)
+        _lib.check(_lib.load().npfem_ibm_spread(self.handle, cell_origins.data_ptr(),
+                                                vertex_f.data_ptr(), dims.ctypes.data, float(dx),
+                                                origin.ctypes.data, out.data_ptr()))
+        return out
+
     def rollout(self, forces: torch.Tensor, dt: float, n_iter: int, n_steps: int, ckpt_every: int):
         """n_steps steps under constant forces, checkpointing every ckpt_every steps."""
         self._check_field(forces, "forces")
@@ -242,4 +304,10 @@ def batch_from_suspension(susp, precision="fp32", device="cuda", per_cell_weight
         alpha, beta = getattr(c, "damping", (0.0, 0.0))
         if alpha or beta:
             b.set_damping(k, alpha, beta)
+    wc = float(susp.extra.get("contact_weight", 0.0))
+    if wc and susp.extra.get("contacts") is not None:
+        pts, nrm, off = susp.extra["contacts"]
+        b.set_contacts(wc, torch.tensor(pts.T, dtype=dt_, device=device).contiguous(),
+                       torch.tensor(nrm.T, dtype=dt_, device=device).contiguous(),
+                       torch.tensor(off, dtype=torch.int32, device=device).contiguous())
     return b, pos, vel, f, meshes
