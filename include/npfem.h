@@ -191,6 +191,25 @@ int npfem_set_weights(npfem_batch b, const double* cell_weights);
  * negative or non-finite coefficients), HIP, OOM. */
 int npfem_set_damping(npfem_batch b, int32_t cls, double alpha, double beta);
 
+/* Solver of the implicit step. history < 0 (the default): classic PD, n_iter
+ * local/global iterations. history >= 0: the quasi-Newton step of the
+ * redesigned PD the solver follows (Implementation and architecture, after
+ * Liu et al.): n_iter L-BFGS iterations on the step's objective
+ *   g(q) = (m/2h^2)|q - s|^2 + sum_i (w_i/2) dist^2(S_i q, C_i)
+ * (gradient A q - b(q), the PD global step's residual) from q^0 = s, with
+ * the PD matrix as initial Hessian (one product with the class operator per
+ * iteration), the last `history` (<= 16) pairs of iterate and gradient
+ * changes (two-loop recursion; a pair with non-positive curvature is kept
+ * inert), and a backtracking line search: alpha = 1, halved while the
+ * objective fails the Armijo test (c = 1e-4), at most line_search rounds
+ * (1..8), the last trial taken if none passes. Each round is one local step
+ * for the cells still searching. history 0 with line_search 1 is PD.
+ * FP64 and FP32 batches only; not with damping or contacts (npfem_step then
+ * fails), nor with npfem_rollout. The first call allocates (4 + 2 history)
+ * column sets and per-cell scalars. Synchronises. Errors: INVALID_ARG, HIP,
+ * OOM. */
+int npfem_set_quasi_newton(npfem_batch b, int32_t history, int32_t line_search);
+
 /* Contact (collision) potentials of every cell against its colliding
  * neighbours, which the caller supplies (the fluid side exchanges them,
  * Implementation and architecture; their strength is the collision weight,

@@ -18,8 +18,11 @@ y_k = grad_{k+1} - grad_k) and applies the inverse-Hessian estimate by the
 standard two-loop recursion with A^-1 in the middle (Nocedal and Wright,
 Algorithm 7.4). The step length comes from backtracking on g: alpha = 1, then
 halved while g(q + alpha d) > g(q) + c alpha grad^T d (Armijo, c = 1e-4), at
-most `max_ls` trials, the last trial taken if none passes. A pair with
-y^T s <= 0 is not stored. With history 0 and full steps this is plain PD.
+most `max_ls` trials, the last trial taken if none passes. Every iteration
+stores its pair in a ring of `history` slots; a pair with y^T s <= 0 gets
+rho = 0, which makes it inert in the recursion (reading: the slot is used
+all the same, so that every cell's history advances in step). With history 0
+and full steps this is plain PD.
 """
 from __future__ import annotations
 
@@ -73,8 +76,8 @@ def step(cs: "S.CellSolver", x, v, f, n_iter, history=5, max_ls=3, record=False)
             alpha *= 0.5
         sk, yk = qn - q, gn - g
         sy = float(np.sum(sk * yk))
-        if history > 0 and sy > 0.0:
-            hist.append((sk, yk, 1.0 / sy))
+        if history > 0:
+            hist.append((sk, yk, 1.0 / sy if sy > 0.0 else 0.0))
             if len(hist) > history:
                 hist.pop(0)
         q, E, g = qn, En, gn

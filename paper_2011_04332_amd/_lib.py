@@ -41,6 +41,7 @@ EXPORTED = [
     "npfem_set_weights",
     "npfem_set_damping",
     "npfem_set_contacts",
+    "npfem_set_quasi_newton",
     "npfem_ibm_interpolate",
     "npfem_ibm_spread",
     "npfem_rollout",
@@ -105,6 +106,7 @@ def load() -> ctypes.CDLL:
     lib.npfem_set_weights.argtypes = [P, P]
     lib.npfem_set_damping.argtypes = [P, I32, D, D]
     lib.npfem_set_contacts.argtypes = [P, D, P, P, P, ctypes.c_int64]
+    lib.npfem_set_quasi_newton.argtypes = [P, I32, I32]
     lib.npfem_ibm_interpolate.argtypes = [P, P, P, P, D, P, P]
     lib.npfem_ibm_spread.argtypes = [P, P, P, P, D, P, P]
     lib.npfem_rollout.argtypes = [P, P, D, I32, I32, I32]

@@ -28,6 +28,7 @@ SOURCES = [
     "kernels_factor.hip",
     "kernels_adjoint.hip",
     "kernels_ibm.hip",
+    "kernels_qn.hip",
 ]
 
 # Packed-FP32 VALU instructions are kept out of all device code: the compiler

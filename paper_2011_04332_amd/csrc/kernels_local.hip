@@ -69,6 +69,7 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
   const int tid = threadIdx.x;
   const int lc = blockIdx.x;
   const int cell = a.cs.cell0 + lc;
+  if (a.skip && a.skip[cell]) return;  // (uniform)
   const long long vb = a.cs.vert0 + (long long)lc * N;
   const long long cb = a.cs.elem0 + 3LL * lc * Npad;
   // per-cell base pointers: everything below indexes with 32-bit offsets

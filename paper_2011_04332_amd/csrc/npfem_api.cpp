@@ -127,6 +127,15 @@ struct npfem_batch_s {
   void* rhs = nullptr;
   void* res = nullptr;
   void* damp = nullptr;         // right-hand side with the stiffness damping term (columns)
+  // quasi-Newton step (npfem_set_quasi_newton): history slots (-1: classic
+  // PD), line-search rounds, buffers
+  int qn_hist = -1;
+  int qn_hist_cap = -1;  // history the column buffer holds
+  int qn_ls = 3;
+  void* qn_cols = nullptr;        // (4 + 2 hist) column sets: r, v, z, d, s_i, y_i
+  double* qn_scal = nullptr;      // [n_cells][kQnStride]
+  double* qn_e = nullptr;         // [2][n_cells] objective: current, trial
+  int* qn_done = nullptr;         // [n_cells]
   // immersed-boundary spreading: 64-bit fixed-point accumulators [3][nodes]
   // and the max |F| word in front of them
   unsigned long long* ibm_acc = nullptr;
@@ -751,8 +760,13 @@ int enqueue_solve(npfem_batch_s* b, ClassState& c, T* B, T* C, const T* D, doubl
 // see kernels_local.hip). Classes touch
 // disjoint parts of every batch buffer, so their chains are independent.
 template <typename T>
+int enqueue_class_step_qn(npfem_batch_s* b, ClassState& c, T* pos, T* vel, const T* forces,
+                          double h, int n_iter, hipStream_t st);
+
+template <typename T>
 int enqueue_class_step(npfem_batch_s* b, ClassState& c, T* pos, T* vel, const T* forces,
                        double h, int n_iter, hipStream_t st, T* const* dslots) {
+  if (b->qn_hist >= 0 && !dslots) return enqueue_class_step_qn<T>(b, c, pos, vel, forces, h, n_iter, st);
   T* delta = static_cast<T*>(b->delta);
   T* delta2 = static_cast<T*>(b->delta2);
   T* cterm = static_cast<T*>(b->cterm);
@@ -808,6 +822,104 @@ int enqueue_class_step(npfem_batch_s* b, ClassState& c, T* pos, T* vel, const T*
   }
   NPFEM_TIMED(NPFEM_KERNEL_UPDATE,
               launch_update<T>(slice_of<T>(c), pos, vel, b->sumN, slot(n_iter), h, st),
+              "update");
+  return NPFEM_OK;
+}
+
+// The quasi-Newton form of a class's step (kernels_qn.hip): predict; the
+// local step at q^0 gives r and the objective; then n_iter times: first loop,
+// product with the class operator, second loop and full-step trial, and up to
+// qn_ls rounds of (local step at the trial for the cells still searching,
+// Armijo test / halving); update. The iterates live in the delta buffer, the
+// trials in delta2, the local step writes r to the QN r buffer (initial) or
+// rhs (trials).
+template <typename T>
+int enqueue_class_step_qn(npfem_batch_s* b, ClassState& c, T* pos, T* vel, const T* forces,
+                          double h, int n_iter, hipStream_t st) {
+  T* delta = static_cast<T*>(b->delta);
+  T* trial = static_cast<T*>(b->delta2);
+  T* cterm = static_cast<T*>(b->cterm);
+  const size_t cs_elems = (size_t)b->total_elems;
+  T* cols = static_cast<T*>(b->qn_cols);
+  QnArgs<T> q{};
+  q.hist = b->qn_hist;
+  q.r_cur = cols;
+  q.v = cols + cs_elems;
+  q.z = cols + 2 * cs_elems;
+  q.d = cols + 3 * cs_elems;
+  for (int i = 0; i < q.hist; ++i) {
+    q.s[i] = cols + (4 + 2 * (size_t)i) * cs_elems;
+    q.y[i] = cols + (5 + 2 * (size_t)i) * cs_elems;
+  }
+  q.r_trial = static_cast<T*>(b->rhs);
+  q.delta = delta;
+  q.delta_trial = trial;
+  q.scal = b->qn_scal;
+  q.stride = kQnStride;
+  q.e_cur = b->qn_e;
+  q.e_trial = b->qn_e + b->n_cells;
+  q.done = b->qn_done;
+  const bool want_energy = (b->flags & NPFEM_OPT_ENERGY) != 0;
+  q.energy = want_energy ? b->energy : nullptr;
+  q.energy_iters = n_iter;
+  q.n_cells = b->n_cells;
+  const T* w = b->per_cell ? static_cast<const T*>(b->weights_dev) : nullptr;
+  NPFEM_TIMED(NPFEM_KERNEL_PREDICT,
+              launch_predict<T>(slice_of<T>(c), pos, vel, forces, b->sumN, delta, cterm,
+                                b->status, h, 0.0, st),
+              "predict");
+  LocalArgs<T> a;
+  a.cs = slice_of<T>(c);
+  a.pos = pos;
+  a.sumN = b->sumN;
+  a.cterm = cterm;
+  a.weights = w;
+  a.colmax = nullptr;
+  a.status = b->status;
+  a.h = h;
+  a.m = c.mat.vertex_mass;
+  a.mdelta = c.mat.vertex_mass / (h * h);
+  a.max_vol_iter = b->max_vol_iter;
+  set_volume_tolerances(a, c, b->fp64);
+  // objective and r at q^0 (recorded as the energy of iterate 0)
+  a.delta = delta;
+  a.rhs = q.r_cur;
+  a.energy = q.e_cur;
+  NPFEM_TIMED(NPFEM_KERNEL_LOCAL, launch_local<T>(a, c.local_block, st), "local step");
+  if (want_energy)
+    HIP_TRY(hipMemcpyAsync(b->energy + c.cell0, q.e_cur + c.cell0, sizeof(double) * c.n_cells,
+                           hipMemcpyDeviceToDevice, st),
+            "energy record");
+  for (int it = 0; it < n_iter; ++it) {
+    const int count = std::min(it, q.hist);
+    const int head = q.hist > 0 ? it % q.hist : 0;
+    HIP_TRY(launch_qn_loop1<T>(slice_of<T>(c), q, count, head, st), "quasi-Newton first loop");
+    GemmArgs g;
+    g.A = c.op;
+    g.A_frag = c.op_frag;
+    g.B = q.v + c.elem0;
+    g.C = q.z + c.elem0;
+    g.D = nullptr;
+    g.colscale = nullptr;
+    g.Npad = c.Npad;
+    g.ncols = 3 * c.n_cells;
+    g.mode = EPI_SET;
+    g.hm = c.hm_eff(h);
+    g.beta = c.beta;
+    NPFEM_TIMED(NPFEM_KERNEL_GLOBAL, launch_gemm(b->gemm_kind, c.gemm_tile, g, st), "global step");
+    HIP_TRY(launch_qn_loop2<T>(slice_of<T>(c), q, count, head, st), "quasi-Newton second loop");
+    for (int t = 0; t < b->qn_ls; ++t) {
+      a.delta = trial;
+      a.rhs = q.r_trial;
+      a.energy = q.e_trial;
+      a.skip = q.done;
+      NPFEM_TIMED(NPFEM_KERNEL_LOCAL, launch_local<T>(a, c.local_block, st), "local step");
+      HIP_TRY(launch_qn_accept<T>(slice_of<T>(c), q, head, t == b->qn_ls - 1 ? 1 : 0, it, st),
+              "quasi-Newton line search");
+    }
+  }
+  NPFEM_TIMED(NPFEM_KERNEL_UPDATE,
+              launch_update<T>(slice_of<T>(c), pos, vel, b->sumN, delta, h, st),
               "update");
   return NPFEM_OK;
 }
@@ -1289,6 +1401,11 @@ int npfem_step(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter)
   if (!ext_forces) return fail(NPFEM_ERR_INVALID_ARG, "ext_forces is NULL");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(NPFEM_ERR_INVALID_ARG, "dt must be finite and > 0");
   if (n_iter < 1 || n_iter > 1000) return fail(NPFEM_ERR_INVALID_ARG, "n_iter must be in [1, 1000]");
+  if (b->qn_hist >= 0)
+    for (const auto& c : b->cls)
+      if (c.alpha != 0.0 || c.beta_d != 0.0 || c.wc != 0.0)
+        return fail(NPFEM_ERR_INVALID_ARG,
+                    "the quasi-Newton step covers the undamped, contact-free objective");
   DeviceGuard guard(b->device);
   int rc;
   if (dt != b->dt) {
@@ -1378,6 +1495,55 @@ int npfem_set_damping(npfem_batch b, int32_t cls, double alpha, double beta) {
   }
   // the operator depends on the damping: refactor and re-capture at the next step
   b->dt = 0.0;
+  if (b->graph) {
+    hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  b->ro_valid = false;
+  return NPFEM_OK;
+}
+
+int npfem_set_quasi_newton(npfem_batch b, int32_t history, int32_t line_search) {
+  g_err.clear();
+  if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
+  if (history > kQnMaxHist || line_search < 1 || line_search > 8)
+    return fail(NPFEM_ERR_INVALID_ARG, "history must be <= 16 and line_search in [1, 8]");
+  if (history >= 0 && b->gemm_kind >= 2)
+    return fail(NPFEM_ERR_INVALID_ARG, "the quasi-Newton step runs FP64 and FP32 batches");
+  DeviceGuard guard(b->device);
+  HIP_TRY(hipStreamSynchronize(b->stream), "sync before solver change");
+  if (history >= 0) {
+    const size_t tsz = b->fp64 ? sizeof(double) : sizeof(float);
+    const size_t need = (4 + 2 * (size_t)history) * tsz * (size_t)b->total_elems;
+    auto drop = [&](void* p) {
+      if (!p) return;
+      auto it = std::find(b->allocs.begin(), b->allocs.end(), p);
+      if (it != b->allocs.end()) b->allocs.erase(it);
+      hipFree(p);
+    };
+    if (history > b->qn_hist_cap || !b->qn_cols) {
+      drop(b->qn_cols);
+      b->qn_cols = nullptr;
+      int rc = dalloc(b, &b->qn_cols, need, "quasi-Newton columns");
+      if (rc) return rc;
+      HIP_TRY(hipMemset(b->qn_cols, 0, need), "memset");
+      b->qn_hist_cap = history;
+    }
+    if (!b->qn_scal) {
+      void* p = nullptr;
+      int rc = dalloc(b, &p, sizeof(double) * kQnStride * (size_t)b->n_cells, "quasi-Newton scalars");
+      if (rc) return rc;
+      b->qn_scal = static_cast<double*>(p);
+      if ((rc = dalloc(b, &p, sizeof(double) * 2 * (size_t)b->n_cells, "quasi-Newton objective")))
+        return rc;
+      b->qn_e = static_cast<double*>(p);
+      if ((rc = dalloc(b, &p, sizeof(int) * (size_t)b->n_cells, "quasi-Newton flags"))) return rc;
+      b->qn_done = static_cast<int*>(p);
+      HIP_TRY(hipMemset(b->qn_scal, 0, sizeof(double) * kQnStride * (size_t)b->n_cells), "memset");
+    }
+  }
+  b->qn_hist = history < 0 ? -1 : history;
+  b->qn_ls = line_search;
   if (b->graph) {
     hipGraphExecDestroy(b->graph);
     b->graph = nullptr;
@@ -1512,6 +1678,8 @@ int npfem_rollout(npfem_batch b, const void* ext_forces, double dt, int32_t n_it
   if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
   if (n_steps < 1 || ckpt_every < 1 || ckpt_every > n_steps)
     return fail(NPFEM_ERR_INVALID_ARG, "need n_steps >= 1 and 1 <= ckpt_every <= n_steps");
+  if (b->qn_hist >= 0)
+    return fail(NPFEM_ERR_INVALID_ARG, "the differentiable rollout runs the classic PD step");
   DeviceGuard guard(b->device);
   const size_t tsz = b->fp64 ? sizeof(double) : sizeof(float);
   const size_t sv = 3 * (size_t)b->sumN;

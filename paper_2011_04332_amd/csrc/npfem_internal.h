@@ -84,6 +84,7 @@ struct LocalArgs {
   const T* contact_n = nullptr;
   const int* contact_off = nullptr;
   long long contact_np = 0;
+  const int* skip = nullptr;  // per cell: nonzero = leave the cell alone (quasi-Newton rounds)
   int max_vol_iter;
   double vol_tol;      // relative settling test of the volume multiplier
   double vol_abs;      // absolute test: |d lam| |grad V|_2 below this (length units)
@@ -164,6 +165,42 @@ hipError_t volume_scratch(double** out);
 template <typename T>
 hipError_t launch_volume(const ClassSlice<T>& cs, const T* pos, long long sumN, double* out,
                          hipStream_t st);
+
+// Quasi-Newton step (kernels_qn.hip). Per-cell scalars, stride kQnStride:
+// [gd, alpha, rho[kQnMaxHist], a[kQnMaxHist]].
+constexpr int kQnMaxHist = 16;
+constexpr int kQnGd = 0, kQnAlpha = 1, kQnRho = 2, kQnA = 2 + kQnMaxHist;
+constexpr int kQnStride = 2 + 2 * kQnMaxHist;
+template <typename T>
+struct QnArgs {
+  T* s[kQnMaxHist];  // history column sets s_i (batch bases)
+  T* y[kQnMaxHist];  // history column sets y_i
+  int hist;          // ring slots (0: no history)
+  T* r_cur;          // r at the current iterate (columns)
+  T* r_trial;        // r at the trial iterate
+  T* v;              // first-loop result (the product's input)
+  T* z;              // the product's output
+  T* d;              // search direction
+  T* delta;          // current iterate (increment form)
+  T* delta_trial;    // trial iterate
+  double* scal;      // [n_cells][stride]
+  int stride;
+  double* e_cur;     // [n_cells] objective at the current iterate
+  double* e_trial;   // [n_cells] objective at the trial iterate
+  int* done;         // [n_cells] 1 once this iteration's step is taken
+  double* energy;    // optional record [energy_iters][n_cells]
+  int energy_iters;
+  int n_cells;
+};
+template <typename T>
+hipError_t launch_qn_loop1(const ClassSlice<T>& cs, const QnArgs<T>& q, int count, int head,
+                           hipStream_t st);
+template <typename T>
+hipError_t launch_qn_loop2(const ClassSlice<T>& cs, const QnArgs<T>& q, int count, int head,
+                           hipStream_t st);
+template <typename T>
+hipError_t launch_qn_accept(const ClassSlice<T>& cs, const QnArgs<T>& q, int head, int last,
+                            int it, hipStream_t st);
 
 // Periodic Cartesian fluid grid of the immersed-boundary transfer
 // (kernels_ibm.hip): node (i, j, k) at (ox, oy, oz) + dx (i, j, k), fields

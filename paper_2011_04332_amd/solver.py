@@ -147,6 +147,10 @@ class Batch:
         """Viscous damping C = alpha m I + beta K_d of class cls (-1: all)."""
         _lib.check(_lib.load().npfem_set_damping(self.handle, int(cls), float(alpha), float(beta)))
 
+    def set_quasi_newton(self, history: int = 5, line_search: int = 3):
+        """L-BFGS implicit step (history >= 0) or classic PD (history < 0)."""
+        _lib.check(_lib.load().npfem_set_quasi_newton(self.handle, int(history), int(line_search)))
+
     def set_contacts(self, weight: float, points=None, normals=None, cell_offsets=None):
         """Contact potentials: points / normals device SoA [3][P] (pos dtype),
         cell_offsets device int32 [n_cells + 1]; weight 0 disables. The

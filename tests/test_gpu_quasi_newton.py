@@ -1,0 +1,103 @@
+"""Quasi-Newton implicit step on the GPU (npfem_set_quasi_newton) against
+the oracle's L-BFGS step (oracle/quasi_newton.py), and its convergence.
+
+Uniform weights: the GPU's initial Hessian is the cell's own PD matrix, as
+in the oracle, so the iterates are compared after a few iterations (FP64
+1e-12, FP32 1e-6 of the cell radius). Per-cell weights: the GPU keeps the
+class's nominal operator as initial Hessian (the oracle factors each cell's
+own), so the iterations differ and the converged steps are compared.
+"""
+import numpy as np
+import pytest
+
+from npfem_workload import suspensions as W
+from oracle import quasi_newton as Q
+from oracle import solver as S
+
+from gpu_helpers import as_precision, log, max_error, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-6}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2011_04332_amd import _lib
+    _lib.load()
+
+
+def _run(s, prec, n_iter, history=5, ls=3, energy=False):
+    import torch
+    from paper_2011_04332_amd import solver
+    b, pos, vel, f, _ = solver.batch_from_suspension(s, precision=prec, energy=energy)
+    b.set_quasi_newton(history, ls)
+    for _ in range(s.n_steps):
+        b.step(f, s.dt, n_iter)
+    b.sync_status()
+    E = b.energy() if energy else None
+    x = pos.double().cpu().numpy()
+    b.close()
+    return x, E
+
+
+def _oracle(s, cells, n_iter, history=5, ls=3):
+    out = {}
+    for c in cells:
+        mc, x0, v0, f, w = s.cell_arrays(int(c))
+        cs = S.CellSolver(S.operators_for(mc), S.Params(tuple(w), mc.mass, s.dt))
+        out[int(c)] = Q.rollout(cs, x0, v0, f, n_iter, s.n_steps, history, ls)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("history", [0, 5])
+def test_lattice_stiff(prec, history):
+    s = W.stiff(W.rbc_lattice(n_cells=16, n_steps=3))
+    s.x0 = s.x0 + 0.03 * np.random.default_rng(3).standard_normal(s.x0.shape)
+    if prec == "fp32":
+        s = as_precision(s, np.float32)
+    cells = [0, 9, 15]
+    log(f"quasi-Newton lattice {prec} history {history}")
+    x, _ = _run(s, prec, 6, history)
+    err = max_error(s, x, _oracle(s, cells, 6, history))
+    log(f"quasi-Newton lattice {prec} history {history} err {err:.3e}")
+    assert err <= TOL[prec]
+
+
+def test_converged_uneven_per_cell_weights_fp32():
+    """RBC + platelet + large classes, per-cell weights: 40 L-BFGS iterations
+    reach the step's minimiser, which the oracle's converged PD step gives."""
+    s = as_precision(W.stiff(W.uneven(n_rbc=4, n_plt=3, n_large=1, n_steps=2)), np.float32)
+    cells = [0, 4, 7]
+    log("quasi-Newton uneven fp32")
+    x, _ = _run(s, "fp32", 40)
+    ref = {}
+    for c in cells:
+        mc, x0, v0, f, w = s.cell_arrays(c)
+        cs = S.CellSolver(S.operators_for(mc), S.Params(tuple(w), mc.mass, s.dt))
+        ref[c] = cs.rollout(x0, v0, f, 400, s.n_steps)
+    err = max_error(s, x, ref)
+    log(f"quasi-Newton uneven fp32 vs converged PD err {err:.3e}")
+    assert err <= TOL["fp32"]
+
+
+def test_faster_than_pd_and_monotone_fp64():
+    """Stiff RBCs (dt 1e-2) from a perturbed shape: after 12 iterations the
+    L-BFGS step is over 100x closer to the converged step than PD after 12
+    (oracle, one cell: 6e-7 against 2.9e-4 of the radius); the recorded
+    objective never increases over the iterations."""
+    s = W.stiff(W.rbc_lattice(n_cells=8, n_steps=1), dt=1e-2)
+    s.x0 = s.x0 + 0.1 * np.random.default_rng(4).standard_normal(s.x0.shape)
+    x_ref, _ = _run(s, "fp64", 100)
+    x_qn, E = _run(s, "fp64", 12, energy=True)
+    x_pd, _ = run_gpu(s, "fp64", n_iter=12)
+    R = 3.91
+    e_qn = np.abs(x_qn - x_ref).max() / R
+    e_pd = np.abs(x_pd - x_ref).max() / R
+    log(f"12 iterations: quasi-Newton {e_qn:.3e}, PD {e_pd:.3e}")
+    assert e_qn <= 1e-2 * e_pd
+    assert np.all(np.diff(E, axis=0) <= 1e-12 * np.abs(E[0]))
