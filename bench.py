@@ -30,7 +30,12 @@ Prints ONE JSON line:
 * single_rbc_fp64: one RBC (162 vertices) in FP64, 100 steps x 20 iterations,
   against the oracle's full run;
 * fwd_bwd: forward + backward time of the differentiation workload (1024
-  RBCs, 50 steps x 10 iterations, checkpoints every 10 steps).
+  RBCs, 50 steps x 10 iterations, checkpoints every 10 steps);
+* next_rows: the further forms on the 4096-RBC lattice, each with its oracle
+  error: viscous damping, wall contacts, the quasi-Newton step against PD at
+  equal iteration counts on the stiff twin (error against the converged
+  step), and the immersed-boundary interpolation and spreading on a periodic
+  160^3 grid.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload precision_sweep]
 """
@@ -273,12 +278,16 @@ def timed_steps(b, f, dt, n_iter, steps):
     return el
 
 
-def run_form(s, precision, n_iter, snap_steps, time_steps, warmup, n_refine=-1, autotune=True):
+def run_form(s, precision, n_iter, snap_steps, time_steps, warmup, n_refine=-1, autotune=True,
+             qn=None):
     """One precision form of a workload: snapshot (positions, volumes) after
     snap_steps steps from the initial state, then time_steps timed steps from
-    the initial state again. Returns a dict with the snapshot and timings."""
+    the initial state again. Returns a dict with the snapshot and timings.
+    qn: (history, line-search rounds) for the quasi-Newton step."""
     import torch
     b, pos, vel, f, meshes = make_batch(s, precision, n_refine=n_refine, autotune=autotune)
+    if qn is not None:
+        b.set_quasi_newton(*qn)
     x0, v0 = pos.clone(), vel.clone()
     for _ in range(max(1, warmup)):
         b.step(f, s.dt, n_iter)
@@ -451,6 +460,7 @@ def main():
     extra = {}
     if not a.no_extra:
         extra = extra_workloads(a)
+        extra["next_rows"] = next_rows(a)
 
     out = {
         "metric": METRIC,
@@ -633,6 +643,132 @@ def extra_workloads(a):
                       "fwd_bwd_ms": round((tf + tb) * 1e3, 3),
                       "backward_over_forward": round(tb / tf, 3)}
     log(f"forward+backward: {out['fwd_bwd']}")
+    return out
+
+
+def _oracle_qn(args):
+    """Worker: the oracle's quasi-Newton rollout of one cell."""
+    susp, c, n_iter, n_steps, hist, ls = args
+    _pin_threads()
+    from oracle import quasi_newton as Q
+    from oracle import solver as S
+    mc, x0, v0, f, w = susp.cell_arrays(int(c))
+    cs = S.CellSolver(S.operators_for(mc), S.Params(tuple(w), mc.mass, susp.dt))
+    x, _ = Q.rollout(cs, x0, v0, f, n_iter, n_steps, hist, ls)
+    return int(c), x
+
+
+def next_rows(a):
+    """Throughput and oracle error of the solver's further forms on the
+    4096-RBC lattice: viscous damping, wall contacts, the quasi-Newton step
+    (stiff twin), and the immersed-boundary transfer."""
+    import torch
+    from npfem_workload import suspensions as W
+    from oracle import solver as S
+    from paper_2011_04332_amd import solver
+    out = {}
+    procs = max(1, min(os.cpu_count() or 1, a.cpu_procs))
+    steps, snap = 50, 10
+    base = lambda: round_inputs(W.rbc_lattice(n_steps=snap))
+    cells = None
+
+    def measure(key, s, n_iter=10, qn=None, oracle=True):
+        nonlocal cells
+        cells = W.sample_cells(s, [3])
+        r = run_form(s, "fp32", n_iter, snap, steps, a.warmup, autotune=not a.no_autotune, qn=qn)
+        e = {"value": round(s.n_cells * n_iter * r["steps"] / r["elapsed"], 1),
+             "unit": "cell-PD-iterations/s", "ms_per_step": round(r["elapsed"] / r["steps"] * 1e3, 4)}
+        if oracle and not a.no_cpu_baseline:
+            ref, _, _ = oracle_cells(s, cells, snap, n_iter, min(procs, len(cells)))
+            e.update(errors_vs_oracle(s, r["snap"], r["vols"], ref))
+            e["bound"] = BOUND["fp32"]
+        return e, r
+
+    # viscous damping: alpha h = 0.02, beta/h = 1
+    s = base()
+    for mc in s.classes:
+        mc.damping = (200.0, 1e-4)
+    out["damping"], _ = measure("damping", s)
+    out["damping"]["workload"] = ("4096 RBC lattice, C = alpha m I + beta K_d with alpha 200/s, "
+                                  "beta 1e-4 s, FP32, 10 PD iterations")
+    # wall contacts under every cell
+    s = W.wall_contacts(base(), depth=0.3)
+    out["contacts"], _ = measure("contacts", s)
+    out["contacts"]["workload"] = ("4096 RBC lattice, each on a plane wall cutting 0.3 um into it, "
+                                   "81 contact points per cell, weight 10, FP32, 10 PD iterations")
+    # quasi-Newton vs PD on the stiff twin (dt 1e-2) from perturbed shapes
+    s = W.stiff(W.rbc_lattice(n_cells=1024, n_steps=snap), dt=1e-2)
+    s.x0 = s.x0 + 0.1 * np.random.default_rng(4).standard_normal(s.x0.shape)
+    s = round_inputs(s)
+    qn_e, rq = measure("qn", s, n_iter=12, qn=(5, 3), oracle=False)
+    pd_e, rp = measure("pd", s, n_iter=12, oracle=False)
+    ref, _ = run_form(s, "fp32", 100, snap, 1, 1, autotune=False, qn=(5, 3))["snap"], None
+    R = 3.91
+    qn_e["err_vs_converged"] = float(np.abs(rq["snap"] - ref).max() / R)
+    pd_e["err_vs_converged"] = float(np.abs(rp["snap"] - ref).max() / R)
+    if not a.no_cpu_baseline:
+        import multiprocessing as mp
+        cq = W.sample_cells(s, [2])
+        with mp.get_context("spawn").Pool(len(cq), initializer=_pin_threads) as pool:
+            res = pool.map(_oracle_qn, [(s, int(c), 12, snap, 5, 3) for c in cq])
+        qn_e["max_rel_pos_err"] = float(max(S.rel_position_error(rq["snap"][:, s.cell_slice(c)].T, x)
+                                            for c, x in res))
+        qn_e["bound"] = BOUND["fp32"]
+    out["quasi_newton"] = {"qn_12_iterations": qn_e, "pd_12_iterations": pd_e,
+                           "workload": f"1024 RBC, dt 1e-2 (stiff twin), shapes perturbed by "
+                                       f"N(0, 0.1^2) um, 12 iterations per step, history 5, 3 "
+                                       f"line-search rounds; errors after {snap} steps, the "
+                                       f"converged step from 100 quasi-Newton iterations"}
+    # immersed-boundary transfer on a periodic 160^3 grid (dx 1 um)
+    s = round_inputs(W.rbc_lattice(n_steps=1))
+    b, pos, vel, f, _ = make_batch(s, "fp32")
+    dims, dx, org0 = (160, 160, 160), 1.0, np.zeros(3)
+    nn = int(np.prod(dims))
+    rng = np.random.default_rng(6)
+    u = torch.tensor(rng.standard_normal((3, nn)), dtype=torch.float32, device="cuda").contiguous()
+    orgs = torch.tensor(s.origins + 5.0, dtype=torch.float64, device="cuda").contiguous()
+    F = torch.tensor(0.05 * rng.standard_normal(tuple(pos.shape)), dtype=torch.float32,
+                     device="cuda").contiguous()
+    U = b.ibm_interpolate(orgs, u, dims, dx, org0)
+    g = b.ibm_spread(orgs, F, dims, dx, org0)
+    reps = 20
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    for _ in range(reps):
+        b.ibm_interpolate(orgs, u, dims, dx, org0, out=U)
+    ev[1].record()
+    ev[2].record()
+    for _ in range(reps):
+        b.ibm_spread(orgs, F, dims, dx, org0, out=g)
+    ev[3].record()
+    torch.cuda.synchronize()
+    b.sync_status()
+    ti = ev[0].elapsed_time(ev[1]) / reps
+    ts = ev[2].elapsed_time(ev[3]) / reps
+    V = pos.shape[1]
+    ibm_e = {"vertices": V, "grid": list(dims), "dx_um": dx,
+             "interpolate_ms": round(ti, 4), "interpolate_vertices_per_s": round(V / (ti * 1e-3), 1),
+             "interpolate_GBs": round((24 * V + 12 * V + 12 * nn) / (ti * 1e-3) / 1e9, 1),
+             "spread_ms": round(ts, 4), "spread_vertices_per_s": round(V / (ts * 1e-3), 1),
+             "spread_GBs": round((24 * V + 12 * V + 36 * nn) / (ts * 1e-3) / 1e9, 1),
+             "bytes_note": "algorithmic: positions and vertex values once, each grid field once "
+                           "(interpolation reads u; spreading clears, accumulates and converts)"}
+    if not a.no_cpu_baseline:
+        from oracle import ibm
+        cs_ = W.sample_cells(s, [2])
+        xh = pos.double().cpu().numpy()
+        Uh = U.double().cpu().numpy()
+        uh = u.double().cpu().numpy().reshape((3,) + dims, order="F")
+        err = 0.0
+        for c in cs_:
+            sl = s.cell_slice(int(c))
+            X = (s.origins[int(c)] + 5.0)[None, :] + xh[:, sl].T
+            ref = ibm.interpolate(uh, X, org0, dx)
+            err = max(err, float(np.abs(Uh[:, sl].T - ref).max() / np.abs(ref).max()))
+        ibm_e["interpolate_max_rel_err"] = err
+    b.close()
+    out["ibm"] = ibm_e
+    log(f"next rows: {out}")
     return out
 
 
