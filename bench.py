@@ -326,8 +326,9 @@ def main():
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--pin-config", default="",
-                    help="local block,tile m,tile n,sweeps for every class (skips the autotuner); "
-                         "profiling runs use it to launch exactly the configuration the timed run chose")
+                    help="local block,tile m,tile n,sweeps, one group per class separated by ';' "
+                         "(a single group applies to every class; skips the autotuner); profiling "
+                         "runs use it to launch exactly the configuration the timed run chose")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the BF16 / FP16 / FP64 forms of the workload")
     ap.add_argument("--no-extra", action="store_true",
@@ -367,11 +368,16 @@ def main():
     log(f"workload {wl}: {desc}; {a.precision}; steps {a.steps} warmup {a.warmup}")
 
     # ---- main timed run (hipGraph replays)
-    pinned = [int(v) for v in a.pin_config.split(",")] if a.pin_config else None
+    pinned = None
+    if a.pin_config:
+        groups = [[int(v) for v in g.split(",")] for g in a.pin_config.split(";")]
+        if len(groups) not in (1, len(s.classes)) or any(len(g) != 4 for g in groups):
+            sys.exit(f"bench.py: --pin-config needs 1 or {len(s.classes)} groups of 4 integers")
+        pinned = groups * len(s.classes) if len(groups) == 1 else groups
     b, pos, vel, f, meshes = make_batch(s, a.precision, autotune=not (a.no_autotune or pinned))
     if pinned:
         for k in range(len(s.classes)):
-            b.set_config(k, pinned)
+            b.set_config(k, pinned[k])
     x_init, v_init = pos.clone(), vel.clone()
     for _ in range(max(1, a.warmup)):
         b.step(f, dt, n_iter)
@@ -585,10 +591,20 @@ def extra_workloads(a):
             e.update(errors_vs_oracle(su, r["snap"], r["vols"], ref))
         res[key] = e
     res["speedup_fp16_vs_fp32"] = round(res["fp16_auto"]["value"] / res["fp32"]["value"], 4)
+    # overlap of the class branches in the step graph: each class alone (its
+    # own batch and graph) against the three together
+    alone = []
+    for k in range(len(su.classes)):
+        sk = su.subset(np.nonzero(su.cell_class == k)[0])
+        rk = run_form(sk, "fp32", su.n_iter, 0, 100, a.warmup, autotune=not a.no_autotune)
+        alone.append(rk["elapsed"] / rk["steps"] * 1e3)
+    res["fp32"]["class_alone_ms_per_step"] = [round(t, 4) for t in alone]
+    res["fp32"]["branch_overlap"] = round(sum(alone) / res["fp32"]["ms_per_step"], 4)
     res["workload"] = ("3000 RBC (642 v) + 600 platelets (162 v) + 64 large cells (2562 v), "
                        "weights +-20 % per cell, forces N(0, 0.05^2), 10 PD iterations, one graph "
                        "per step with a branch per class, autotuned launch shapes; errors after "
-                       f"{snap_steps} steps on cells {[int(c) for c in cells]}")
+                       f"{snap_steps} steps on cells {[int(c) for c in cells]}; branch_overlap = "
+                       "sum of the classes' step times alone / their step time together")
     out["uneven"] = res
     log(f"uneven: {res}")
 
@@ -696,29 +712,34 @@ def next_rows(a):
     out["contacts"], _ = measure("contacts", s)
     out["contacts"]["workload"] = ("4096 RBC lattice, each on a plane wall cutting 0.3 um into it, "
                                    "81 contact points per cell, weight 10, FP32, 10 PD iterations")
-    # quasi-Newton vs PD on the stiff twin (dt 1e-2) from perturbed shapes
-    s = W.stiff(W.rbc_lattice(n_cells=1024, n_steps=snap), dt=1e-2)
+    # quasi-Newton vs PD on the stiff twin (dt 1e-2) from perturbed shapes:
+    # one step's distance from the converged step at equal iteration counts
+    s = W.stiff(W.rbc_lattice(n_cells=1024, n_steps=1), dt=1e-2)
     s.x0 = s.x0 + 0.1 * np.random.default_rng(4).standard_normal(s.x0.shape)
     s = round_inputs(s)
-    qn_e, rq = measure("qn", s, n_iter=12, qn=(5, 3), oracle=False)
-    pd_e, rp = measure("pd", s, n_iter=12, oracle=False)
-    ref, _ = run_form(s, "fp32", 100, snap, 1, 1, autotune=False, qn=(5, 3))["snap"], None
     R = 3.91
-    qn_e["err_vs_converged"] = float(np.abs(rq["snap"] - ref).max() / R)
-    pd_e["err_vs_converged"] = float(np.abs(rp["snap"] - ref).max() / R)
+    ref = run_form(s, "fp64", 100, 1, 1, 1, autotune=False, qn=(5, 3))["snap"]
+    qn_e, pd_e = {}, {}
+    for e, qn in ((qn_e, (5, 3)), (pd_e, None)):
+        r = run_form(s, "fp32", 12, 1, steps, a.warmup, autotune=not a.no_autotune, qn=qn)
+        e.update({"value": round(s.n_cells * 12 * r["steps"] / r["elapsed"], 1),
+                  "unit": "cell-iterations/s", "ms_per_step": round(r["elapsed"] / r["steps"] * 1e3, 4),
+                  "err_vs_converged": float(np.abs(r["snap"] - ref).max() / R)})
+        if qn is not None:
+            rq = r
     if not a.no_cpu_baseline:
         import multiprocessing as mp
         cq = W.sample_cells(s, [2])
         with mp.get_context("spawn").Pool(len(cq), initializer=_pin_threads) as pool:
-            res = pool.map(_oracle_qn, [(s, int(c), 12, snap, 5, 3) for c in cq])
+            res = pool.map(_oracle_qn, [(s, int(c), 12, 1, 5, 3) for c in cq])
         qn_e["max_rel_pos_err"] = float(max(S.rel_position_error(rq["snap"][:, s.cell_slice(c)].T, x)
                                             for c, x in res))
         qn_e["bound"] = BOUND["fp32"]
     out["quasi_newton"] = {"qn_12_iterations": qn_e, "pd_12_iterations": pd_e,
-                           "workload": f"1024 RBC, dt 1e-2 (stiff twin), shapes perturbed by "
-                                       f"N(0, 0.1^2) um, 12 iterations per step, history 5, 3 "
-                                       f"line-search rounds; errors after {snap} steps, the "
-                                       f"converged step from 100 quasi-Newton iterations"}
+                           "workload": "1024 RBC, dt 1e-2 (stiff twin), shapes perturbed by "
+                                       "N(0, 0.1^2) um, one step of 12 iterations, history 5, 3 "
+                                       "line-search rounds, FP32; the converged step from 100 "
+                                       "quasi-Newton iterations in FP64"}
     # immersed-boundary transfer on a periodic 160^3 grid (dx 1 um)
     s = round_inputs(W.rbc_lattice(n_steps=1))
     b, pos, vel, f, _ = make_batch(s, "fp32")

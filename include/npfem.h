@@ -201,8 +201,9 @@ int npfem_set_damping(npfem_batch b, int32_t cls, double alpha, double beta);
  * iteration), the last `history` (<= 16) pairs of iterate and gradient
  * changes (two-loop recursion; a pair with non-positive curvature is kept
  * inert), and a backtracking line search: alpha = 1, halved while the
- * objective fails the Armijo test (c = 1e-4), at most line_search rounds
- * (1..8), the last trial taken if none passes. Each round is one local step
+ * objective fails the Armijo test (c = 1e-4; FP32 batches allow an increase
+ * of 2^-20 of the objective, the rounding of an FP32 state's objective), at
+ * most line_search rounds (1..8), the last trial taken if none passes. Each round is one local step
  * for the cells still searching. history 0 with line_search 1 is PD.
  * FP64 and FP32 batches only; not with damping or contacts (npfem_step then
  * fails), nor with npfem_rollout. The first call allocates (4 + 2 history)

@@ -21,7 +21,9 @@
 // back. S is a power of two chosen from max |F| so that no node sum can
 // exceed 2^62 / S: with n vertices and |phi phi phi| <= 1/8,
 //   S = 2^floor(log2(2^62 / (n max|F| / (8 dx^3)))),
-// which keeps ~40 bits below the largest possible contribution.
+// which keeps ~40 bits below the largest possible contribution. A cell's
+// contributions are first summed in LDS over the box of nodes its vertices
+// reach (ibm_spread_box_kernel), then added to the grid once per node.
 #include <algorithm>
 #include <cmath>
 
@@ -132,12 +134,35 @@ __device__ __forceinline__ double ibm_scale(const unsigned long long* mx, double
   return ldexp(1.0, max(-1000, min(1000, e)));
 }
 
+// Spreading, one workgroup per cell. The cell's vertices touch a box of grid
+// nodes (their supports), which the workgroup sums with 64-bit LDS atomics
+// and then adds to the grid with one global atomic per touched node and
+// component (instead of one per vertex, node and component). The box is
+// found from the vertices' lowest and highest support nodes; a box beyond
+// the LDS budget, or a non-finite or far-off coordinate, sends the cell's
+// contributions to the grid directly, one global atomic each. The same
+// integers either way, so the same (bitwise) result.
+constexpr int kIbmBoxNodes = 2688;  // 3 x 8 bytes each: 63 KB of LDS
+
+__device__ __forceinline__ double block_min_d(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int w = 1; w < (int)blockDim.x / kWave; ++w) r = fmin(r, red[w]);
+  return r;
+}
+
 template <typename T>
-__global__ void __launch_bounds__(256) ibm_spread_kernel(
+__global__ void __launch_bounds__(256) ibm_spread_box_kernel(
     ClassSlice<T> cs, const T* __restrict__ pos, long long sumN,
     const double* __restrict__ origins, const T* __restrict__ f, IbmGrid g,
     const unsigned long long* __restrict__ mx, double n_total,
     unsigned long long* __restrict__ acc) {
+  __shared__ unsigned long long box[3 * kIbmBoxNodes];
+  __shared__ double red[256 / kWave];
   const int lc = blockIdx.x;
   const int cell = cs.cell0 + lc;
   const int N = cs.cv.N;
@@ -146,6 +171,43 @@ __global__ void __launch_bounds__(256) ibm_spread_kernel(
   const long long nn = (long long)g.nx * g.ny * g.nz;
   const double idx = 1.0 / g.dx;
   const double S = ibm_scale(mx, n_total, g.dx) / (g.dx * g.dx * g.dx);
+  // the cell's support box: lowest and highest floor of the grid coordinate
+  // per axis (unwrapped node units)
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int bad = 0;
+  for (int v = threadIdx.x; v < N; v += blockDim.x) {
+    const long long e = vb + v;
+    const double sv[3] = {(ox + (double)pos[e] - g.ox) * idx, (oy + (double)pos[sumN + e] - g.oy) * idx,
+                          (oz + (double)pos[2 * sumN + e] - g.oz) * idx};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double fl = floor(sv[d]);
+      if (!(fabs(fl) < 1e9)) {
+        bad = 1;
+      } else {
+        lo[d] = fmin(lo[d], fl);
+        hi[d] = fmax(hi[d], fl);
+      }
+    }
+  }
+  bool fits = !__syncthreads_or(bad);  // (uniform)
+  int b0[3] = {0, 0, 0}, bn[3] = {4, 4, 4};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double l = block_min_d(lo[d], red), h = -block_min_d(-hi[d], red);
+    if (fits && h - l + 4.0 <= (double)kIbmBoxNodes) {
+      b0[d] = (int)l - 1;  // the lowest support node, floor - 1
+      bn[d] = (int)(h - l) + 4;
+    } else {
+      fits = false;
+    }
+  }
+  const long long vol = (long long)bn[0] * bn[1] * bn[2];
+  fits = fits && vol <= kIbmBoxNodes;
+  if (fits) {
+    for (int i = threadIdx.x; i < 3 * vol; i += blockDim.x) box[i] = 0ull;
+    __syncthreads();
+  }
   for (int v = threadIdx.x; v < N; v += blockDim.x) {
     const long long e = vb + v;
     int i0, j0, k0;
@@ -154,20 +216,45 @@ __global__ void __launch_bounds__(256) ibm_spread_kernel(
     peskin4<double>((oy + (double)pos[sumN + e] - g.oy) * idx, j0, wy);
     peskin4<double>((oz + (double)pos[2 * sumN + e] - g.oz) * idx, k0, wz);
     const double fs[3] = {(double)f[e] * S, (double)f[sumN + e] * S, (double)f[2 * sumN + e] * S};
+    // the box holds every support by construction; checked all the same
+    const bool inb = fits && (unsigned)(i0 - b0[0]) <= (unsigned)(bn[0] - 4) &&
+                     (unsigned)(j0 - b0[1]) <= (unsigned)(bn[1] - 4) &&
+                     (unsigned)(k0 - b0[2]) <= (unsigned)(bn[2] - 4);
     for (int c = 0; c < 4; ++c) {
-      const int kk = wrap(k0 + c, g.nz);
       for (int b = 0; b < 4; ++b) {
-        const long long row = (long long)g.nx * (wrap(j0 + b, g.ny) + (long long)g.ny * kk);
         const double wbc = wy[b] * wz[c];
+        const long long row = inb ? (long long)bn[0] * ((j0 + b - b0[1]) + (long long)bn[1] * (k0 + c - b0[2]))
+                                  : (long long)g.nx * (wrap(j0 + b, g.ny) + (long long)g.ny * wrap(k0 + c, g.nz));
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-          const long long n = row + wrap(i0 + a, g.nx);
           const double wt = wx[a] * wbc;
+          if (inb) {
+            const long long n = row + (i0 + a - b0[0]);
 #pragma unroll
-          for (int d = 0; d < 3; ++d)
-            atomicAdd(acc + d * nn + n, (unsigned long long)llrint(wt * fs[d]));
+            for (int d = 0; d < 3; ++d)
+              atomicAdd(box + d * vol + n, (unsigned long long)llrint(wt * fs[d]));
+          } else {
+            const long long n = row + wrap(i0 + a, g.nx);
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+              atomicAdd(acc + d * nn + n, (unsigned long long)llrint(wt * fs[d]));
+          }
         }
       }
+    }
+  }
+  if (!fits) return;
+  __syncthreads();
+  for (long long i = threadIdx.x; i < vol; i += blockDim.x) {
+    const int a = (int)(i % bn[0]);
+    const int b = (int)((i / bn[0]) % bn[1]);
+    const int c = (int)(i / ((long long)bn[0] * bn[1]));
+    const long long n = wrap(b0[0] + a, g.nx) +
+                        (long long)g.nx * (wrap(b0[1] + b, g.ny) + (long long)g.ny * wrap(b0[2] + c, g.nz));
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const unsigned long long v = box[d * vol + i];
+      if (v) atomicAdd(acc + d * nn + n, v);
     }
   }
 }
@@ -216,7 +303,7 @@ hipError_t launch_ibm_spread(const ClassSlice<T>& cs, const T* pos, long long su
                              const unsigned long long* mx, double n_total,
                              unsigned long long* acc, hipStream_t st) {
   if (cs.n_cells == 0) return hipSuccess;
-  hipLaunchKernelGGL(ibm_spread_kernel<T>, dim3(cs.n_cells), dim3(256), 0, st, cs, pos, sumN,
+  hipLaunchKernelGGL(ibm_spread_box_kernel<T>, dim3(cs.n_cells), dim3(256), 0, st, cs, pos, sumN,
                      origins, f, g, mx, n_total, acc);
   return hipGetLastError();
 }

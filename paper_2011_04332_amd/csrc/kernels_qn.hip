@@ -12,7 +12,9 @@
 //   qn_loop2:   for oldest..newest: z += (a_i - rho_i y_i.z) s_i; d = -z;
 //               gd = g.d; alpha = 1; trial = delta + d
 //   (local step at the trial: its r and objective)
-//   qn_accept:  Armijo E_trial <= E + c alpha gd (or the last round): store
+//   qn_accept:  Armijo E_trial <= E + c alpha gd + e_tol |E| (or the last
+//               round; e_tol covers the rounding of an FP32 state's objective,
+//               0 for FP64): store
 //               s = trial - delta, y = r - r_trial, rho = 1/(s.y) (0 when
 //               s.y <= 0: the pair is inert), take the trial; else halve
 //               alpha and form the next trial.
@@ -143,7 +145,7 @@ __global__ void __launch_bounds__(kQnBlock) qn_accept_kernel(ClassSlice<T> cs, Q
   double* sc = q.scal + c.cell * q.stride;
   const double E = q.e_cur[c.cell], Et = q.e_trial[c.cell];
   const double alpha = sc[kQnAlpha];
-  const bool take = last || Et <= E + kArmijo * alpha * sc[kQnGd];
+  const bool take = last || Et <= E + kArmijo * alpha * sc[kQnGd] + q.e_tol * fabs(E);
   if (take) {
     T* __restrict__ si = q.hist > 0 ? q.s[head] + c.cb : nullptr;
     T* __restrict__ yi = q.hist > 0 ? q.y[head] + c.cb : nullptr;

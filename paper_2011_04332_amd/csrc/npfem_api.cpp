@@ -859,6 +859,10 @@ int enqueue_class_step_qn(npfem_batch_s* b, ClassState& c, T* pos, T* vel, const
   q.e_cur = b->qn_e;
   q.e_trial = b->qn_e + b->n_cells;
   q.done = b->qn_done;
+  // an FP32 state rounds the objective to ~1e-7 of itself: near convergence
+  // the Armijo decrease falls below that, and without an allowance every
+  // trial would be rejected
+  q.e_tol = b->fp64 ? 0.0 : std::ldexp(1.0, -20);
   const bool want_energy = (b->flags & NPFEM_OPT_ENERGY) != 0;
   q.energy = want_energy ? b->energy : nullptr;
   q.energy_iters = n_iter;

@@ -188,6 +188,7 @@ struct QnArgs {
   double* e_cur;     // [n_cells] objective at the current iterate
   double* e_trial;   // [n_cells] objective at the trial iterate
   int* done;         // [n_cells] 1 once this iteration's step is taken
+  double e_tol;      // Armijo allowance relative to |E| (state rounding)
   double* energy;    // optional record [energy_iters][n_cells]
   int energy_iters;
   int n_cells;

@@ -2,7 +2,7 @@
 npfem_ibm_spread) against the oracle (oracle/ibm.py), and the solid step
 coupled to a synthetic flow through them.
 
-Cells sit in a periodic 48 x 40 x 44 grid (dx 0.5 um), some across the
+Cells sit in a periodic 48 x 40 x 44 grid (dx 0.5 um) or 24 x 20 x 22 (dx 1 um), some across the
 periodic seam. Bounds: FP64 interpolation 1e-13 and spreading 1e-11 of the
 largest value (the spreading's 64-bit fixed point keeps ~40 bits below the
 largest possible contribution); FP32 1e-6 (FP32 weights and sums).
@@ -30,13 +30,13 @@ def gpu():
     _lib.load()
 
 
-def _setup(prec, n_rbc=4, n_plt=2):
+def _setup(prec, dims=DIMS, dx=DX, n_rbc=4, n_plt=2):
     """A small RBC + platelet batch placed in the periodic box (the last cell
     straddles the seam)."""
     s = W.precision_sweep(n_rbc=n_rbc, n_plt=n_plt, n_steps=3)
     if prec == "fp32":
         s = as_precision(s, np.float32)
-    L = DX * np.array(DIMS)
+    L = dx * np.array(dims)
     rng = np.random.default_rng(4)
     org = ORIGIN + rng.uniform(0.2, 0.8, (s.n_cells, 3)) * L
     org[-1] = ORIGIN + L - 0.3  # across the seam
@@ -52,21 +52,26 @@ def _global(s, x, org):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_interpolate_and_spread(prec):
+@pytest.mark.parametrize("dx", [0.5, 1.0])
+def test_interpolate_and_spread(prec, dx):
+    """dx 0.5: a cell's support box exceeds the spreading kernel's LDS box
+    (global atomics per contribution); dx 1.0: it fits (LDS box, one global
+    atomic per node)."""
     import torch
     from paper_2011_04332_amd import solver
-    s, org = _setup(prec)
+    dims = DIMS if dx == 0.5 else (24, 20, 22)
+    s, org = _setup(prec, dims, dx)
     b, pos, vel, f, _ = solver.batch_from_suspension(s, precision=prec)
     dt_ = pos.dtype
     rng = np.random.default_rng(5)
-    u = rng.standard_normal((3,) + DIMS)
+    u = rng.standard_normal((3,) + dims)
     ug = torch.tensor(u.reshape(3, -1, order="F"), dtype=dt_, device="cuda").contiguous()
     u_ref = u.astype(np.float32).astype(np.float64) if prec == "fp32" else u
     orgd = torch.tensor(org, dtype=torch.float64, device="cuda").contiguous()
     X = _global(s, pos.double().cpu().numpy(), org)
     log(f"ibm interpolate {prec}")
-    U = b.ibm_interpolate(orgd, ug, DIMS, DX, ORIGIN)
-    U_ref = ibm.interpolate(u_ref, X, ORIGIN, DX)
+    U = b.ibm_interpolate(orgd, ug, dims, dx, ORIGIN)
+    U_ref = ibm.interpolate(u_ref, X, ORIGIN, dx)
     err = np.abs(U.double().cpu().numpy().T - U_ref).max() / np.abs(U_ref).max()
     log(f"ibm interpolate {prec} rel err {err:.3e}")
     assert err <= (1e-13 if prec == "fp64" else 1e-6)
@@ -74,17 +79,17 @@ def test_interpolate_and_spread(prec):
     Fg = torch.tensor(F, dtype=dt_, device="cuda").contiguous()
     F_ref = Fg.double().cpu().numpy().T
     log(f"ibm spread {prec}")
-    g1 = b.ibm_spread(orgd, Fg, DIMS, DX, ORIGIN)
-    g2 = b.ibm_spread(orgd, Fg, DIMS, DX, ORIGIN)
+    g1 = b.ibm_spread(orgd, Fg, dims, dx, ORIGIN)
+    g2 = b.ibm_spread(orgd, Fg, dims, dx, ORIGIN)
     b.sync_status()
     assert torch.equal(g1, g2)  # bitwise reproducible
-    f_ref = ibm.spread(F_ref, X, DIMS, ORIGIN, DX).reshape(3, -1, order="F")
+    f_ref = ibm.spread(F_ref, X, dims, ORIGIN, dx).reshape(3, -1, order="F")
     got = g1.double().cpu().numpy()
     err = np.abs(got - f_ref).max() / np.abs(f_ref).max()
     log(f"ibm spread {prec} rel err {err:.3e}")
     assert err <= (1e-11 if prec == "fp64" else 1e-6)
     if prec == "fp64":  # total force conserved
-        assert np.allclose(got.sum(1) * DX ** 3, F_ref.sum(0), rtol=0, atol=1e-12)
+        assert np.allclose(got.sum(1) * dx ** 3, F_ref.sum(0), rtol=0, atol=1e-12)
     b.close()
 
 
