@@ -713,20 +713,28 @@ def next_rows(a):
     out["contacts"]["workload"] = ("4096 RBC lattice, each on a plane wall cutting 0.3 um into it, "
                                    "81 contact points per cell, weight 10, FP32, 10 PD iterations")
     # quasi-Newton vs PD on the stiff twin (dt 1e-2) from perturbed shapes:
-    # one step's distance from the converged step at equal iteration counts
+    # one step's distance from the converged step (per cell, max over its
+    # vertices / R) after equal iteration counts, median and max over cells
     s = W.stiff(W.rbc_lattice(n_cells=1024, n_steps=1), dt=1e-2)
     s.x0 = s.x0 + 0.1 * np.random.default_rng(4).standard_normal(s.x0.shape)
     s = round_inputs(s)
     R = 3.91
     ref = run_form(s, "fp64", 100, 1, 1, 1, autotune=False, qn=(5, 3))["snap"]
-    qn_e, pd_e = {}, {}
-    for e, qn in ((qn_e, (5, 3)), (pd_e, None)):
-        r = run_form(s, "fp32", 12, 1, steps, a.warmup, autotune=not a.no_autotune, qn=qn)
-        e.update({"value": round(s.n_cells * 12 * r["steps"] / r["elapsed"], 1),
-                  "unit": "cell-iterations/s", "ms_per_step": round(r["elapsed"] / r["steps"] * 1e3, 4),
-                  "err_vs_converged": float(np.abs(r["snap"] - ref).max() / R)})
-        if qn is not None:
-            rq = r
+
+    def cell_errs(snap):
+        d = np.abs(snap - ref).max(axis=0) / R
+        return np.array([d[s.cell_slice(c)].max() for c in range(s.n_cells)])
+
+    curve, rq = {}, None
+    for k in (12, 24, 48):
+        for name, qn in (("qn", (5, 3)), ("pd", None)):
+            r = run_form(s, "fp32", k, 1, 20, a.warmup, autotune=not a.no_autotune, qn=qn)
+            ce = cell_errs(r["snap"])
+            curve[f"{name}_{k}"] = {"ms_per_step": round(r["elapsed"] / r["steps"] * 1e3, 4),
+                                   "err_median": float(np.median(ce)), "err_max": float(ce.max())}
+            if name == "qn" and k == 12:
+                rq = r
+    qn_e = dict(curve["qn_12"])
     if not a.no_cpu_baseline:
         import multiprocessing as mp
         cq = W.sample_cells(s, [2])
@@ -735,11 +743,12 @@ def next_rows(a):
         qn_e["max_rel_pos_err"] = float(max(S.rel_position_error(rq["snap"][:, s.cell_slice(c)].T, x)
                                             for c, x in res))
         qn_e["bound"] = BOUND["fp32"]
-    out["quasi_newton"] = {"qn_12_iterations": qn_e, "pd_12_iterations": pd_e,
+    out["quasi_newton"] = {"qn_12_iterations_vs_oracle": qn_e, "convergence": curve,
                            "workload": "1024 RBC, dt 1e-2 (stiff twin), shapes perturbed by "
-                                       "N(0, 0.1^2) um, one step of 12 iterations, history 5, 3 "
-                                       "line-search rounds, FP32; the converged step from 100 "
-                                       "quasi-Newton iterations in FP64"}
+                                       "N(0, 0.1^2) um, one step of k iterations (quasi-Newton: "
+                                       "history 5, 3 line-search rounds; PD), FP32; errors per "
+                                       "cell against the converged step (100 quasi-Newton "
+                                       "iterations in FP64), in units of the cell radius"}
     # immersed-boundary transfer on a periodic 160^3 grid (dx 1 um)
     s = round_inputs(W.rbc_lattice(n_steps=1))
     b, pos, vel, f, _ = make_batch(s, "fp32")

@@ -23,7 +23,8 @@
 // vertex), and the per-element contributions, which each vertex then gathers
 // through fixed-width incidence lists in a fixed order (no atomics): results
 // are bitwise reproducible. Triangles and hinges go through LDS in chunks
-// sized to the budget; chunking does not change the summation order.
+// sized to the budget (a vertex adds its entries chunk by chunk, each chunk's
+// in list order).
 #include <algorithm>
 
 #include "device_utils.h"
