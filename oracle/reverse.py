@@ -189,8 +189,40 @@ def step(ct: TorchCell, x, v, f, w, m, h, n_iter, chol=None):
     return q, (q - x) / h
 
 
+def _step_vjp_along_iterates(ct: TorchCell, xn, vn, fn, wn, m, h, q_given, gx, gv):
+    """Vector-Jacobian product of one step whose iterates q^1 .. q^K are given
+    (q_given, K = n_iter; q^0 = s): every iteration q^{k+1} = A(w)^-1 rhs(q^k)
+    is differentiated at the given q^k, and the adjoints are chained by hand
+    from the last iterate back to s. Returns (dx, dv, dw, df)."""
+    xn = xn.clone().requires_grad_(True)
+    vn = vn.clone().requires_grad_(True)
+    wn = wn.clone().requires_grad_(True)
+    fn = fn.clone().requires_grad_(True)
+    chol = system_factor(ct, wn, m, h)
+    s = xn + h * vn + (h * h / m) * fn
+    K = len(q_given)
+    # x' = q^K, v' = (q^K - x)/h
+    g = gx + gv / h
+    gw = torch.zeros_like(wn)
+    gs = torch.zeros_like(s)
+    for k in range(K - 1, -1, -1):
+        if k == 0:
+            phi = torch.cholesky_solve(rhs(s, s, ct, wn, m, h), chol)
+            ds, dw = torch.autograd.grad(phi, (s, wn), g, retain_graph=True)
+            gs = gs + ds
+        else:
+            qk = q_given[k - 1].clone().requires_grad_(True)
+            phi = torch.cholesky_solve(rhs(qk, s, ct, wn, m, h), chol)
+            dq, ds, dw = torch.autograd.grad(phi, (qk, s, wn), g, retain_graph=True)
+            g = dq
+            gs = gs + ds
+        gw = gw + dw
+    dx, dv, df = torch.autograd.grad(s, (xn, vn, fn), gs)
+    return dx - gv / h, dv, gw, df
+
+
 def rollout_grad(o: ops_mod.CellOperators, weights, mass, dt, x0, v0, f, target, n_iter,
-                 n_steps, round_state=None, states=None, x_final=None):
+                 n_steps, round_state=None, states=None, x_final=None, iterates=None):
     """L = sum |x_T - target|^2 and its gradients.
 
     Returns (L, dL/dw [4], dL/df [N,3], dL/dx0 [N,3], dL/dv0 [N,3]), float64
@@ -208,11 +240,23 @@ def rollout_grad(o: ops_mod.CellOperators, weights, mass, dt, x0, v0, f, target,
     them) and x_final the positions after the last step, e.g. the states a
     reduced-precision solver went through. Each step's derivative is taken
     at the given state (FP64), so the result is the exact gradient of the
-    composed step maps along that trajectory."""
+    composed step maps along that trajectory.
+
+    iterates (with states): iterates[n] = [q^1, ..., q^n_iter] of step n as
+    the other solver formed them; every PD iteration is then differentiated at
+    the given iterate instead of at the oracle's own (x_final defaults to the
+    last step's last iterate). With the oracle's own iterates this is the
+    same gradient."""
     ct = TorchCell(o)
     m, h = float(mass), float(dt)
     w_val = _t(np.asarray(weights, dtype=np.float64))
     f_val = _t(f)
+    if iterates is not None:
+        assert states is not None and len(iterates) == n_steps
+        iterates = [[_t(q) for q in its] for its in iterates]
+        assert all(len(its) == n_iter for its in iterates)
+        if x_final is None:
+            x_final = iterates[-1][-1].numpy()
     if states is not None:
         assert len(states) == n_steps and x_final is not None
         states = [(_t(a), _t(b)) for a, b in states]
@@ -233,6 +277,13 @@ def rollout_grad(o: ops_mod.CellOperators, weights, mass, dt, x0, v0, f, target,
     gw = torch.zeros(4, dtype=DT)
     gf = torch.zeros_like(f_val)
     for n in range(n_steps - 1, -1, -1):
+        if iterates is not None:
+            dx, dv, dw, df = _step_vjp_along_iterates(ct, states[n][0], states[n][1], f_val,
+                                                      w_val, m, h, iterates[n], gx, gv)
+            gx, gv = dx, dv
+            gw += dw
+            gf += df
+            continue
         xn = states[n][0].clone().requires_grad_(True)
         vn = states[n][1].clone().requires_grad_(True)
         wn = w_val.clone().requires_grad_(True)

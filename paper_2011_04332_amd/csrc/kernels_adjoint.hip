@@ -20,10 +20,14 @@
 //
 // The element arithmetic runs in FP64 also for FP32 state (see the kernel).
 // The weight-gradient residuals P_i(q) - S_i q' are formed in displacement
-// form, (P_i(q) - S_i q) + S_i (q - q') with q - q' = delta^k - delta^{k+1}
-// taken from the delta columns and the volume's P(q) - q = lam grad V taken
-// from the projection itself: near rest the residual is far smaller than the
-// positions, and q - q' evaluated from rounded positions would lose it.
+// form, (P_i(q) - S_i q) + S_i (q - q'), and the volume's P(q) - q = lam grad V
+// is taken from the projection itself: near rest the residual is far smaller
+// than the positions. q is the point the forward local step projected, the
+// rounded sum x + delta^k, while the forward's next iterate is x + delta^{k+1}
+// held as its increment; so q - q' = (q - x) - delta^{k+1}, formed in FP64
+// from the stored values (q - x is exact there), which keeps the rounding of
+// q itself (an ulp of the coordinates, for FP32 state as large as the
+// residual's own scale near rest) and of positions rebuilt from q' out of it.
 #include <algorithm>
 
 #include "device_utils.h"
@@ -94,12 +98,13 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
   int bad = 0;
   double wacc[4] = {0.0, 0.0, 0.0, 0.0};
 
-  // the records of vertex v: q = x + delta_0, delta_0 - delta_1, lambda
+  // the records of vertex v: q = x + delta_0 (rounded as the forward staged
+  // it), q - q' = (q - x) - delta_1, lambda
   auto fetch = [&](int v, V4<T>& q, V4<T>& dd, V4<T>& l) {
     const T x0 = px[v], x1 = py[v], x2 = pz[v];
     q = V4<T>{x0 + d0[v], x1 + d0[Npad + v], x2 + d0[2 * Npad + v], T(0)};
-    dd = V4<T>{d0[v] - d1[v], d0[Npad + v] - d1[Npad + v], d0[2 * Npad + v] - d1[2 * Npad + v],
-               T(0)};
+    dd = V4<T>{T(((A)q.x - (A)x0) - (A)d1[v]), T(((A)q.y - (A)x1) - (A)d1[Npad + v]),
+               T(((A)q.z - (A)x2) - (A)d1[2 * Npad + v]), T(0)};
     l = V4<T>{lcol[v], lcol[Npad + v], lcol[2 * Npad + v], T(0)};
   };
   if constexpr (VPT <= 4) {

@@ -68,15 +68,19 @@ def max_error(susp, x_gpu, ref):
 
 def reverse_along(args):
     """Worker (spawned process): the oracle's FP64 reverse-mode gradient of
-    one cell along the trajectory another solver went through."""
+    one cell along the trajectory another solver went through
+    (susp, cell, target, step-start states, final positions[, the PD
+    iterates of every step])."""
     import os
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     import torch
     torch.set_num_threads(1)
     from oracle import reverse as R
-    susp, c, tgt, states, x_final = args
+    susp, c, tgt, states, x_final = args[:5]
+    iterates = args[5] if len(args) > 5 else None
     mc, x0, v0, f, w = susp.cell_arrays(int(c))
     o = S.operators_for(mc)
     _, gw, gf, _, _ = R.rollout_grad(o, w, mc.mass, susp.dt, x0, v0, f, tgt, susp.n_iter,
-                                     susp.n_steps, states=states, x_final=x_final)
+                                     susp.n_steps, states=states, x_final=x_final,
+                                     iterates=iterates)
     return int(c), gw, gf

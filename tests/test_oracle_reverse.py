@@ -199,3 +199,28 @@ def test_given_trajectory_equals_own_trajectory():
                                       states=states, x_final=x)
     assert abs(L1 - L2) <= 1e-12 * L1
     assert np.allclose(gw1, gw2, rtol=1e-10, atol=0) and np.allclose(gf1, gf2, rtol=1e-10, atol=1e-14)
+
+
+def test_given_iterates_equal_own_iterates():
+    """Differentiating every PD iteration at given iterates reproduces the
+    gradient when the iterates are the oracle's own (q^k after k iterations
+    of its numpy step), and moves it when an iterate is moved."""
+    s, mc, x0, v0, f, w, tgt = _cell(True, n_steps=2, n_iter=3)
+    o = S.operators_for(mc)
+    cs = S.CellSolver(o, S.Params(tuple(w), mc.mass, s.dt))
+    states, its, x, v = [], [], x0, v0
+    for _ in range(2):
+        states.append((x, v))
+        its.append([cs.step(x, v, f, k)[0] for k in (1, 2, 3)])
+        x, v, _ = cs.step(x, v, f, 3)
+    L1, gw1, gf1, gx1, gv1 = R.rollout_grad(o, w, mc.mass, s.dt, x0, v0, f, tgt, 3, 2)
+    L2, gw2, gf2, gx2, gv2 = R.rollout_grad(o, w, mc.mass, s.dt, x0, v0, f, tgt, 3, 2,
+                                            states=states, iterates=its)
+    assert abs(L1 - L2) <= 1e-12 * L1
+    for a, b in ((gw1, gw2), (gf1, gf2), (gx1, gx2), (gv1, gv2)):
+        assert np.abs(a - b).max() <= 1e-10 * np.abs(a).max()
+    moved = [list(q) for q in its]
+    moved[0][1] = moved[0][1] + 1e-3 * o.radius
+    _, gw3, *_ = R.rollout_grad(o, w, mc.mass, s.dt, x0, v0, f, tgt, 3, 2,
+                                states=states, iterates=moved)
+    assert np.abs(gw3 - gw1).max() > 1e-6 * np.abs(gw1).max()
