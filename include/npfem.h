@@ -146,9 +146,11 @@ int npfem_mesh_system_matrix(npfem_mesh m, const double* weights4, double dt, do
  *                 updated in place by npfem_step
  *   opt           options (NULL = FP32, defaults)
  * Allocates device workspace; the FP64 factorisation happens at the first
- * step (it depends on the time step). Errors: INVALID_ARG (also for an FP64
- * batch with a mesh of more than 2550 vertices, whose local step does not fit
- * the 160 KB of LDS of a CU), HIP, OOM. */
+ * step (it depends on the time step). Errors: INVALID_ARG (also for a mesh
+ * of more than 5632 vertices, beyond the local step's widest workgroup of
+ * 512 threads x 11 vertices, and for an FP64 batch with a mesh of more than
+ * 2550 vertices, whose local step does not fit the 160 KB of LDS of a CU),
+ * HIP, OOM. */
 int npfem_create_batch(const npfem_mesh* meshes, int32_t n_meshes, const int32_t* cell_mesh,
                        int32_t n_cells, const double* cell_weights, void* pos, void* vel,
                        const npfem_options* opt, npfem_batch* out);

@@ -546,7 +546,7 @@ static LocalFn<T> pick_vpt(int N, int DT, int DH, bool ring) {
   if (vpt <= 4) return pick_widths<T, BLOCK, 4>(DT, DH, ring);
   if (vpt <= 6) return pick_widths<T, BLOCK, 6>(DT, DH, ring);
   if (vpt <= 8) return local_kernel<T, BLOCK, 8, 0, 0>;
-  if (vpt <= 11) return local_kernel<T, BLOCK, 11, 0, 0>;
+  if (vpt <= kLocalMaxVertsPerThread) return local_kernel<T, BLOCK, kLocalMaxVertsPerThread, 0, 0>;
   return nullptr;
 }
 

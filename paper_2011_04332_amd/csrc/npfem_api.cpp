@@ -1345,6 +1345,12 @@ int npfem_create_batch(const npfem_mesh* meshes, int32_t n_meshes, const int32_t
     c.vert0 = vert;
     c.local_block = default_local_block(c.N);
     c.gemm_tile = (3LL * n >= 1024) ? 3 : 0;
+    if (n > 0 && c.N > kLocalMaxBlock * kLocalMaxVertsPerThread)
+      return fail(NPFEM_ERR_INVALID_ARG,
+                  "a batch takes meshes of at most %d vertices (the local step holds at most %d "
+                  "vertices per thread of a %d-thread workgroup); this class has %d",
+                  kLocalMaxBlock * kLocalMaxVertsPerThread, kLocalMaxVertsPerThread,
+                  kLocalMaxBlock, c.N);
     if (b->fp64 && n > 0) {
       // the FP64 local step keeps q and the volume iterate as 32-byte
       // records of N + 1 vertices each in LDS

@@ -57,6 +57,11 @@ struct ClassSlice {
   T w_nom[4];        // nominal weights
 };
 
+// The local step's widest instance: 512 threads with at most 11 vertices
+// each, so a class may have at most 5632 vertices.
+constexpr int kLocalMaxBlock = 512;
+constexpr int kLocalMaxVertsPerThread = 11;
+
 // Kernel launch helpers (defined in the .hip files). All take the stream last.
 struct StepScalars {
   double h;       // time step

@@ -1,0 +1,73 @@
+"""Edge cases of the GPU step against the oracle: a mesh class with no
+cells in the batch, a one-cell batch, a single PD iteration per step, and
+meshes beyond the local step's limits refused at batch creation."""
+import numpy as np
+import pytest
+
+from npfem_workload import meshes, suspensions as W
+
+from gpu_helpers import as_precision, log, max_error, oracle_cells, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-6}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2011_04332_amd import _lib
+    _lib.load()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_mesh_class_without_cells(prec):
+    """RBC and platelet classes with cells, the large class with none (its
+    operators are built, its launches skipped); stiff twin, 2 steps x 4
+    iterations, every cell against the oracle."""
+    s = W.stiff(W.uneven(n_rbc=5, n_plt=3, n_large=0, n_steps=2, n_iter=4))
+    if prec == "fp32":
+        s = as_precision(s, np.float32)
+    assert not np.any(s.cell_class == 2) and len(s.classes) == 3
+    log(f"empty class {prec}")
+    x, _ = run_gpu(s, prec)
+    err = max_error(s, x, oracle_cells(s, range(s.n_cells)))
+    log(f"empty class {prec} err {err:.3e}")
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_one_cell_one_iteration(prec):
+    """One RBC, 5 stiff steps of a single PD iteration each."""
+    s = W.stiff(W.rbc_lattice(n_cells=1, n_steps=5, n_iter=1))
+    if prec == "fp32":
+        s = as_precision(s, np.float32)
+    log(f"one cell one iteration {prec}")
+    x, _ = run_gpu(s, prec)
+    err = max_error(s, x, oracle_cells(s, [0]))
+    log(f"one cell one iteration {prec} err {err:.3e}")
+    assert err <= TOL[prec]
+
+
+def test_mesh_beyond_local_step_refused():
+    """A 10242-vertex sphere (level 5) exceeds the widest local-step
+    workgroup (512 threads x 11 vertices): refused at creation, FP32 too."""
+    from paper_2011_04332_amd import _lib, solver
+    s = W.uneven(n_rbc=1, n_plt=1, n_large=1, n_steps=1)
+    big = W.large_class(5)
+    s = W.Suspension([s.classes[0], s.classes[1], big], s.cell_class, s.origins,
+                     *_restate(s, big), s.dt, s.n_iter, s.n_steps, "too-large")
+    with pytest.raises(_lib.NpfemError) as e:
+        solver.batch_from_suspension(s, precision="fp32")
+    assert e.value.code == _lib.ERR_INVALID_ARG and "5632" in str(e.value)
+
+
+def _restate(s, big):
+    """State arrays with the last cell replaced by the big class's rest shape."""
+    keep = s.cell_slice(s.n_cells - 1).start
+    xb = big.rest.T
+    cat = lambda a, b: np.concatenate([a[:, :keep], b], axis=1)
+    return (cat(s.x0, xb), cat(s.v0, np.zeros_like(xb)), cat(s.forces, np.zeros_like(xb)),
+            s.weights.copy())
