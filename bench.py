@@ -12,7 +12,8 @@ Prints ONE JSON line:
 * roofline: the dominant kernel's algorithmic work per launch over its average
   duration (per-kernel HIP events in a second, eagerly launched pass over the
   same steps), the other kernels' fractions (local step against the FP32
-  VALU, predict and update against HBM), and the whole step's ideal time
+  VALU peak without packed FP32, 78.6 TFLOP/s; predict and update against
+  HBM), and the whole step's ideal time
   sum_k max(flops_k / peak, bytes_k / HBM) over the measured step time;
 * cpu_baseline: the FP64 oracle on the host cores on a bounded sample of
   cells (one process per cell on all cores used, and one cell alone on one
@@ -59,6 +60,11 @@ PEAK = {  # MI355X published peaks
     "fp32_vector_TF": 157.3,
     "fp64_vector_TF": 78.6,
 }
+# FP32 VALU peak this build can reach: 256 CUs x 4 SIMDs x 16 lanes x 2 flops
+# (FMA) x 2.4 GHz. The published 157.3 counts packed FP32 (two lanes per
+# instruction), which this build does not emit (every kernel is compiled
+# without packed-FP32 instructions).
+ALU_FP32_UNPACKED_TF = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 DTYPE = {"fp32": "f32", "fp64": "f64", "bf16": "bf16+f32", "fp16": "f16+f32"}
 BOUND = {"fp64": 1e-12, "fp32": 1e-6, "bf16": 1e-5, "fp16": 1e-5}
 
@@ -503,7 +509,7 @@ def roofline(s, a, kt, launch_cfgs, elapsed, bitwise, wl):
     n_iter, steps = a.n_iter, a.steps
     traffic = measured_traffic(wl, a.precision)
     sweeps = launch_cfgs[0][3]
-    vec_peak = PEAK["fp64_vector_TF"] if a.precision == "fp64" else PEAK["fp32_vector_TF"]
+    vec_peak = PEAK["fp64_vector_TF"] if a.precision == "fp64" else ALU_FP32_UNPACKED_TF
     mat_peak = PEAK[f"{a.precision}_matrix_TF"]
     op_elem = {"fp64": 8, "fp32": 4}.get(a.precision, 2)
     work = {  # (flops, bytes) of all launches of a kind over the timed steps
@@ -523,7 +529,9 @@ def roofline(s, a, kt, launch_cfgs, elapsed, bitwise, wl):
         if kind == "local":
             e = {"bound": "alu", "kernel": "local_kernel (projections + RHS gather)",
                  "algorithmic_flops": fl / n, "algorithmic_hbm_bytes": by / n,
-                 "alu_peak_without_packed_fp32": 78.6}
+                 "peak_derivation": "256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz (FP32 "
+                                    "VALU without packed FP32, which this build does not emit)",
+                 "published_fp32_vector_peak_packed": PEAK["fp32_vector_TF"]}
             ach, peak, unit = fl / (ms * 1e-3) / 1e12, vec_peak, "TFLOP/s"
             e["hbm_GBs"] = round(by / (ms * 1e-3) / 1e9, 1)
         elif kind == "global":
@@ -549,14 +557,14 @@ def roofline(s, a, kt, launch_cfgs, elapsed, bitwise, wl):
     t_ideal /= steps
     t_meas = elapsed / steps
     fl_loc, _ = work["local"]
-    t_ideal_78 = t_ideal - fl_loc / steps / (vec_peak * 1e12) + fl_loc / steps / (78.6e12)
+    t_ideal_pk = t_ideal - fl_loc / steps / (vec_peak * 1e12) + fl_loc / steps / (PEAK["fp32_vector_TF"] * 1e12)
     roof.update({
         "dominant_kernel": dom,
         "other_kernels": {k: v for k, v in entries.items() if k != dom},
         "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in kt.items()},
         "whole_step": {"t_ideal_ms": round(t_ideal * 1e3, 4), "t_measured_ms": round(t_meas * 1e3, 4),
                        "frac": round(t_ideal / t_meas, 4),
-                       "frac_local_at_78.6TF": round(t_ideal_78 / t_meas, 4)},
+                       "frac_local_at_packed_157.3TF": round(t_ideal_pk / t_meas, 4)},
         "timing_pass_bitwise_equal": bitwise,
     })
     return roof
