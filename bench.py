@@ -608,11 +608,26 @@ def extra_workloads(a):
         alone.append(rk["elapsed"] / rk["steps"] * 1e3)
     res["fp32"]["class_alone_ms_per_step"] = [round(t, 4) for t in alone]
     res["fp32"]["branch_overlap"] = round(sum(alone) / res["fp32"]["ms_per_step"], 4)
+    # the same 100 steps as ONE graph launch (npfem_run)
+    bu, pu, vu, fu, _ = make_batch(su, "fp32", autotune=not a.no_autotune)
+    xu, uu = pu.clone(), vu.clone()
+    bu.run(fu, su.dt, su.n_iter, 100)  # captures the run's graph
+    bu.sync_status()
+    pu.copy_(xu)
+    vu.copy_(uu)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bu.run(fu, su.dt, su.n_iter, 100)
+    torch.cuda.synchronize()
+    res["fp32"]["one_launch_ms_per_step"] = round((time.perf_counter() - t0) / 100 * 1e3, 4)
+    bu.sync_status()
+    bu.close()
     res["workload"] = ("3000 RBC (642 v) + 600 platelets (162 v) + 64 large cells (2562 v), "
                        "weights +-20 % per cell, forces N(0, 0.05^2), 10 PD iterations, one graph "
                        "per step with a branch per class, autotuned launch shapes; errors after "
                        f"{snap_steps} steps on cells {[int(c) for c in cells]}; branch_overlap = "
-                       "sum of the classes' step times alone / their step time together")
+                       "sum of the classes' step times alone / their step time together; "
+                       "one_launch_ms_per_step: the 100 steps as one graph launch")
     out["uneven"] = res
     log(f"uneven: {res}")
 

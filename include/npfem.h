@@ -167,6 +167,19 @@ int npfem_create_batch(const npfem_mesh* meshes, int32_t n_meshes, const int32_t
  * NONFINITE (only with NPFEM_OPT_SYNC_CHECK), HIP, OOM. */
 int npfem_step(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter);
 
+/* n_steps calls of npfem_step (same forces, dt and n_iter) as ONE launch: the
+ * uneven batch's whole run, every step with its branch per mesh class, is
+ * captured into one graph at the first call with these arguments (forces
+ * pointer, n_iter, n_steps) and replayed afterwards; results are bitwise
+ * those of the step-by-step calls. For runs of solid steps with no exchange
+ * in between: the solid's own time steps between two fluid-solid exchanges
+ * (the time discretisation is per solver, Implementation and architecture)
+ * and the cell-packing application's thousands of solid-only steps
+ * (Applications, cell packing). With NPFEM_OPT_NO_GRAPH or
+ * NPFEM_OPT_KERNEL_TIMING the steps are launched one by one.
+ * Errors: as npfem_step; INVALID_ARG for n_steps < 1 or > 1000. */
+int npfem_run(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter, int32_t n_steps);
+
 /* Replaces the per-cell weights (host [n_cells][4]: stretch, area, bend,
  * volume; NULL = each class's nominal material). The class operators stay
  * those of the nominal material; cells whose weights differ are solved with

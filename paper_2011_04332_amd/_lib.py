@@ -38,6 +38,7 @@ EXPORTED = [
     "npfem_mesh_system_matrix",
     "npfem_create_batch",
     "npfem_step",
+    "npfem_run",
     "npfem_set_weights",
     "npfem_set_damping",
     "npfem_set_contacts",
@@ -103,6 +104,7 @@ def load() -> ctypes.CDLL:
     lib.npfem_create_batch.argtypes = [P, I32, P, I32, P, P, P, ctypes.POINTER(Options),
                                        ctypes.POINTER(P)]
     lib.npfem_step.argtypes = [P, P, D, I32]
+    lib.npfem_run.argtypes = [P, P, D, I32, I32]
     lib.npfem_set_weights.argtypes = [P, P]
     lib.npfem_set_damping.argtypes = [P, I32, D, D]
     lib.npfem_set_contacts.argtypes = [P, D, P, P, P, ctypes.c_int64]

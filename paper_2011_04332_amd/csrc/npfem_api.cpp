@@ -163,6 +163,10 @@ struct npfem_batch_s {
   hipGraphExec_t graph = nullptr;
   const void* graph_forces = nullptr;
   int graph_iters = 0;
+  // npfem_run: n_steps steps captured as one graph
+  hipGraphExec_t run_graph = nullptr;
+  const void* run_forces = nullptr;
+  int run_iters = 0, run_steps = 0;
   std::vector<void*> allocs;
   // differentiable rollout: checkpoints and recompute workspace
   void* ckpt = nullptr;          // [n_seg][2][3][sumN] positions then velocities
@@ -238,6 +242,7 @@ struct npfem_batch_s {
 
   ~npfem_batch_s() {
     if (graph) hipGraphExecDestroy(graph);
+    if (run_graph) hipGraphExecDestroy(run_graph);
     for (hipStream_t s : br_stream) hipStreamDestroy(s);
     for (hipEvent_t e : br_join) hipEventDestroy(e);
     if (br_fork) hipEventDestroy(br_fork);
@@ -985,6 +990,49 @@ int prepare_kernels(npfem_batch_s* b) {
   return NPFEM_OK;
 }
 
+// Drops the captured step and run graphs (their kernels' arguments or the
+// work they enqueue changed).
+void drop_graphs(npfem_batch_s* b) {
+  if (b->graph) {
+    hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  if (b->run_graph) {
+    hipGraphExecDestroy(b->run_graph);
+    b->run_graph = nullptr;
+  }
+}
+
+// Captures n_steps consecutive steps (each with its branch per class) as one
+// graph: a run replays as a single launch.
+int capture_run_graph(npfem_batch_s* b, const void* forces, double h, int n_iter, int n_steps) {
+  if (b->run_graph) {
+    hipGraphExecDestroy(b->run_graph);
+    b->run_graph = nullptr;
+  }
+  int rc = prepare_kernels(b);
+  if (rc) return rc;
+  HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  for (int i = 0; i < n_steps && !rc; ++i) rc = enqueue_any(b, forces, h, n_iter, b->cap_stream, true);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+  if (rc) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "end capture");
+  e = hipGraphInstantiate(&b->run_graph, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    b->run_graph = nullptr;
+    return hip_fail(e, "graph instantiate");
+  }
+  b->run_forces = forces;
+  b->run_iters = n_iter;
+  b->run_steps = n_steps;
+  return NPFEM_OK;
+}
+
 int capture_graph(npfem_batch_s* b, const void* forces, double h, int n_iter) {
   if (b->graph) {
     hipGraphExecDestroy(b->graph);
@@ -1405,9 +1453,9 @@ int npfem_create_batch(const npfem_mesh* meshes, int32_t n_meshes, const int32_t
   return NPFEM_OK;
 }
 
-int npfem_step(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter) {
-  g_err.clear();
-  if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
+// Argument checks, refactorisation on a new dt and the energy record's
+// size, shared by npfem_step and npfem_run (b checked, device current).
+static int step_prepare(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter) {
   if (!ext_forces) return fail(NPFEM_ERR_INVALID_ARG, "ext_forces is NULL");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(NPFEM_ERR_INVALID_ARG, "dt must be finite and > 0");
   if (n_iter < 1 || n_iter > 1000) return fail(NPFEM_ERR_INVALID_ARG, "n_iter must be in [1, 1000]");
@@ -1416,7 +1464,6 @@ int npfem_step(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter)
       if (c.alpha != 0.0 || c.beta_d != 0.0 || c.wc != 0.0)
         return fail(NPFEM_ERR_INVALID_ARG,
                     "the quasi-Newton step covers the undamped, contact-free objective");
-  DeviceGuard guard(b->device);
   int rc;
   if (dt != b->dt) {
     HIP_TRY(hipStreamSynchronize(b->stream), "sync before refactorisation");
@@ -1425,10 +1472,7 @@ int npfem_step(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter)
       if ((rc = b->fp64 ? autotune<double>(b, dt) : autotune<float>(b, dt))) return rc;
       b->tuned = true;
     }
-    if (b->graph) {
-      hipGraphExecDestroy(b->graph);
-      b->graph = nullptr;
-    }
+    drop_graphs(b);
   }
   if ((b->flags & NPFEM_OPT_ENERGY) && n_iter > b->energy_cap) {
     HIP_TRY(hipStreamSynchronize(b->stream), "sync before energy buffer");
@@ -1442,11 +1486,17 @@ int npfem_step(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter)
     b->allocs.push_back(p);
     b->energy = static_cast<double*>(p);
     b->energy_cap = n_iter;
-    if (b->graph) {
-      hipGraphExecDestroy(b->graph);
-      b->graph = nullptr;
-    }
+    drop_graphs(b);
   }
+  return NPFEM_OK;
+}
+
+int npfem_step(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter) {
+  g_err.clear();
+  if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
+  DeviceGuard guard(b->device);
+  int rc;
+  if ((rc = step_prepare(b, ext_forces, dt, n_iter))) return rc;
   if (b->flags & (NPFEM_OPT_NO_GRAPH | NPFEM_OPT_KERNEL_TIMING)) {
     if ((rc = prepare_kernels(b))) return rc;
     if ((rc = enqueue_any(b, ext_forces, dt, n_iter, b->stream))) return rc;
@@ -1455,6 +1505,29 @@ int npfem_step(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter)
       if ((rc = capture_graph(b, ext_forces, dt, n_iter))) return rc;
     }
     HIP_TRY(hipGraphLaunch(b->graph, b->stream), "graph launch");
+  }
+  b->energy_iters = n_iter;
+  if (b->flags & NPFEM_OPT_SYNC_CHECK) return npfem_sync_status(b);
+  return NPFEM_OK;
+}
+
+int npfem_run(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter, int32_t n_steps) {
+  g_err.clear();
+  if (!b || b->tag != kBatchTag) return fail(NPFEM_ERR_INVALID_ARG, "not a batch handle");
+  if (n_steps < 1 || n_steps > 1000) return fail(NPFEM_ERR_INVALID_ARG, "n_steps must be in [1, 1000]");
+  DeviceGuard guard(b->device);
+  int rc;
+  if ((rc = step_prepare(b, ext_forces, dt, n_iter))) return rc;
+  if (b->flags & (NPFEM_OPT_NO_GRAPH | NPFEM_OPT_KERNEL_TIMING)) {
+    if ((rc = prepare_kernels(b))) return rc;
+    for (int i = 0; i < n_steps; ++i)
+      if ((rc = enqueue_any(b, ext_forces, dt, n_iter, b->stream))) return rc;
+  } else {
+    if (!b->run_graph || b->run_forces != ext_forces || b->run_iters != n_iter ||
+        b->run_steps != n_steps) {
+      if ((rc = capture_run_graph(b, ext_forces, dt, n_iter, n_steps))) return rc;
+    }
+    HIP_TRY(hipGraphLaunch(b->run_graph, b->stream), "graph launch");
   }
   b->energy_iters = n_iter;
   if (b->flags & NPFEM_OPT_SYNC_CHECK) return npfem_sync_status(b);
@@ -1472,10 +1545,7 @@ int npfem_set_weights(npfem_batch b, const double* cell_weights) {
   DeviceGuard guard(b->device);
   HIP_TRY(hipStreamSynchronize(b->stream), "sync before weight update");
   const int rc = apply_weights(b, cell_weights);
-  if (b->graph) {
-    hipGraphExecDestroy(b->graph);
-    b->graph = nullptr;
-  }
+  drop_graphs(b);
   b->ro_valid = false;
   return rc;
 }
@@ -1505,10 +1575,7 @@ int npfem_set_damping(npfem_batch b, int32_t cls, double alpha, double beta) {
   }
   // the operator depends on the damping: refactor and re-capture at the next step
   b->dt = 0.0;
-  if (b->graph) {
-    hipGraphExecDestroy(b->graph);
-    b->graph = nullptr;
-  }
+  drop_graphs(b);
   b->ro_valid = false;
   return NPFEM_OK;
 }
@@ -1554,10 +1621,7 @@ int npfem_set_quasi_newton(npfem_batch b, int32_t history, int32_t line_search) 
   }
   b->qn_hist = history < 0 ? -1 : history;
   b->qn_ls = line_search;
-  if (b->graph) {
-    hipGraphExecDestroy(b->graph);
-    b->graph = nullptr;
-  }
+  drop_graphs(b);
   b->ro_valid = false;
   return NPFEM_OK;
 }
@@ -1584,10 +1648,7 @@ int npfem_set_contacts(npfem_batch b, double weight, const void* points, const v
   // the weight is in the operator (refactor); the arrays' addresses are in
   // the captured graph (re-capture)
   if (refactor) b->dt = 0.0;
-  if (b->graph) {
-    hipGraphExecDestroy(b->graph);
-    b->graph = nullptr;
-  }
+  drop_graphs(b);
   b->ro_valid = false;
   return NPFEM_OK;
 }
@@ -1843,10 +1904,7 @@ int npfem_set_batch_config(npfem_batch b, int32_t cls, const int32_t in[4]) {
     b->n_refine = in[3];
   }
   b->tuned = true;
-  if (b->graph) {
-    hipGraphExecDestroy(b->graph);
-    b->graph = nullptr;
-  }
+  drop_graphs(b);
   return NPFEM_OK;
 }
 

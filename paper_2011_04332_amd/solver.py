@@ -133,6 +133,15 @@ class Batch:
         self._forces = forces  # keep alive while the graph may reference it
         _lib.check(_lib.load().npfem_step(self.handle, forces.data_ptr(), float(dt), int(n_iter)))
 
+    def run(self, forces: torch.Tensor, dt: float, n_iter: int, n_steps: int):
+        """n_steps steps as one graph launch (npfem_run)."""
+        if not (forces.is_cuda and forces.dtype == self.dtype and forces.is_contiguous()
+                and tuple(forces.shape) == tuple(self.pos.shape)):
+            raise ValueError("forces must match pos (contiguous CUDA, same dtype and shape)")
+        self._forces = forces
+        _lib.check(_lib.load().npfem_run(self.handle, forces.data_ptr(), float(dt), int(n_iter),
+                                         int(n_steps)))
+
     def sync_status(self):
         _lib.check(_lib.load().npfem_sync_status(self.handle))
 

@@ -71,3 +71,39 @@ def _restate(s, big):
     cat = lambda a, b: np.concatenate([a[:, :keep], b], axis=1)
     return (cat(s.x0, xb), cat(s.v0, np.zeros_like(xb)), cat(s.forces, np.zeros_like(xb)),
             s.weights.copy())
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_run_as_one_launch_equals_steps(prec):
+    """npfem_run: the uneven batch (three classes, per-cell weights) for 6
+    steps as one graph launch gives bitwise the positions and velocities of 6
+    npfem_step calls, twice in a row (the captured run replays), and the
+    oracle's within the bound (FP32)."""
+    import torch
+    from paper_2011_04332_amd import solver
+    s = W.stiff(W.uneven(n_rbc=6, n_plt=4, n_large=2, n_steps=6, n_iter=3))
+    if prec == "fp32":
+        s = as_precision(s, np.float32)
+    # (fixed launch shapes: two autotuned batches may pick different ones)
+    b1, p1, v1, f1, _ = solver.batch_from_suspension(s, precision=prec, autotune=False)
+    for _ in range(s.n_steps):
+        b1.step(f1, s.dt, s.n_iter)
+    b1.sync_status()
+    b2, p2, v2, f2, _ = solver.batch_from_suspension(s, precision=prec, autotune=False)
+    x0, u0 = p2.clone(), v2.clone()
+    log(f"run {prec}: one launch of {s.n_steps} steps")
+    for rep in range(2):
+        p2.copy_(x0)
+        v2.copy_(u0)
+        b2.run(f2, s.dt, s.n_iter, s.n_steps)
+        b2.sync_status()
+        torch.cuda.synchronize()
+        assert torch.equal(p1, p2) and torch.equal(v1, v2), rep
+    if prec == "fp32":
+        err = max_error(s, p2.double().cpu().numpy(), oracle_cells(s, [0, 6, 10]))
+        log(f"run fp32 err {err:.3e}")
+        assert err <= TOL["fp32"]
+    with pytest.raises(Exception):
+        b2.run(f2, s.dt, s.n_iter, 0)
+    b1.close()
+    b2.close()
