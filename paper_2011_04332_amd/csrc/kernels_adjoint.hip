@@ -56,9 +56,11 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
   extern __shared__ double smem_adj[];
   constexpr int NW = BLOCK / kWave;
   // Element arithmetic (projections, their VJPs and the weight-gradient
-  // residuals) in FP64 for both state types: near rest the residuals
-  // P_i(q) - S_i q are ~1e-3 of the O(1) terms they are formed from, and
-  // the weight gradients sum them against lam with heavy cancellation.
+  // residuals) in FP64 for both state types, from FP64 element records (G,
+  // area, K, c, r): near rest the residuals P_i(q) - S_i q are ~1e-3 of the
+  // O(1) terms they are formed from, and the weight gradients sum them
+  // against lam with heavy cancellation, so an FP32 rounding of G or K alone
+  // moves them by ~1e-3 (a rest shape perturbed at 1e-7).
   using A = double;
   const AdjArgs<T>& a = L.a;
   const ClassView<T>& cv = a.cs.cv;
@@ -136,16 +138,89 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
   {
     V4<T>* ps = reinterpret_cast<V4<T>*>(work);  // N + 1 records
     V4<T>* gs = ps + N + 1;                      // N + 1 records
-    T g[VPT][3], pv[VPT][3];
-    const int no_ring[VPT][1] = {};
-    const double mu = volume_project<T, BLOCK, VPT, true>(cv, qs, ps, red, g, pv, a.max_vol_iter,
-                                                          a.vol_tol, a.vol_abs, bad, no_ring);
+    // The projection p = q + mu grad V(p), V(p) = V_rest (the fixed point of
+    // the forward's volume step) in FP64 arithmetic for both state types:
+    // the iterate is kept as its displacement from q, which is small, so T
+    // records (in gs while iterating) hold it far below the rounding of q.
+    // Near rest mu grad V is the volume weight's residual itself, and an
+    // FP32 evaluation of V(q) would carry ~1e-3 of it.
+    T g[VPT][3];
+    A gd[VPT][3];
+    A mu = A(0);
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const int v = tid + j * BLOCK;
+      if (v < N) gs[v] = V4<T>{T(0), T(0), T(0), T(0)};
+    }
+    if (tid == 0) gs[N] = V4<T>{T(0), T(0), T(0), T(0)};
+    __syncthreads();
+    const int passes = max(2, a.max_vol_iter);
+    for (int it = 0; it < passes; ++it) {
+      double sv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int j = 0; j < VPT; ++j) {
+        const int v = tid + j * BLOCK;
+        gd[j][0] = gd[j][1] = gd[j][2] = A(0);
+        if (v < N) {
+          // grad_v V(p) = (1/6) sum over the fan of p_b x p_c, p = q + d
+          const int* __restrict__ fix = cv.vt_fan + v * DT;
+          for (int k = 0; k < DT; ++k) {
+            const int bc = fix[k], ib = bc & 0xffff, ic = bc >> 16;
+            const V4<T> qb = qs[ib], db = gs[ib], qc = qs[ic], dc = gs[ic];
+            const A bx = (A)qb.x + (A)db.x, by = (A)qb.y + (A)db.y, bz = (A)qb.z + (A)db.z;
+            const A cx = (A)qc.x + (A)dc.x, cy = (A)qc.y + (A)dc.y, cz = (A)qc.z + (A)dc.z;
+            gd[j][0] += by * cz - bz * cy;
+            gd[j][1] += bz * cx - bx * cz;
+            gd[j][2] += bx * cy - by * cx;
+          }
+          const V4<T> qv = qs[v], dv = gs[v];
+          const A dd3[3] = {(A)dv.x, (A)dv.y, (A)dv.z};
+          const A pp[3] = {(A)qv.x + dd3[0], (A)qv.y + dd3[1], (A)qv.z + dd3[2]};
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            gd[j][d] *= A(1.0 / 6.0);
+            sv[0] += pp[d] * gd[j][d];
+            sv[1] += gd[j][d] * gd[j][d];
+            sv[2] -= gd[j][d] * dd3[d];  // grad V . (q - p)
+          }
+        }
+      }
+      block_sum<3>(sv, red);
+      const A mu_new = (cv.vol_rest - sv[0] / 3.0 - sv[2]) / sv[1];
+      if (!isfinite(mu_new)) bad = 1;
+      const bool conv = it > 0 && fabs(mu_new - mu) <= 1e-14 * fabs(mu_new);  // (uniform)
+      mu = isfinite(mu_new) ? mu_new : A(0);
+      __syncthreads();  // every read of the displacement records is done
+#pragma unroll
+      for (int j = 0; j < VPT; ++j) {
+        const int v = tid + j * BLOCK;
+        if (v < N) gs[v] = V4<T>{T(mu * gd[j][0]), T(mu * gd[j][1]), T(mu * gd[j][2]), T(0)};
+      }
+      __syncthreads();
+      if (conv) break;
+    }
+    // p and grad V(p) as records for the Hessian products below
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const int v = tid + j * BLOCK;
+      g[j][0] = T(gd[j][0]);
+      g[j][1] = T(gd[j][1]);
+      g[j][2] = T(gd[j][2]);
+      if (v < N) {
+        const V4<T> qv = qs[v], dv = gs[v];
+        ps[v] = V4<T>{T((A)qv.x + (A)dv.x), T((A)qv.y + (A)dv.y), T((A)qv.z + (A)dv.z), T(0)};
+      }
+    }
+    __syncthreads();  // every displacement record is read
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
       if (v < N) gs[v] = V4<T>{g[j][0], g[j][1], g[j][2], T(0)};
     }
-    if (tid == 0) gs[N] = V4<T>{T(0), T(0), T(0), T(0)};
+    if (tid == 0) {
+      ps[N] = V4<T>{T(0), T(0), T(0), T(0)};
+      gs[N] = V4<T>{T(0), T(0), T(0), T(0)};
+    }
     __syncthreads();
     const T mt = T(mu);
     T u[VPT][3], w[VPT][3];
@@ -185,10 +260,10 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
         }
         r[0] += (double)(g[j][0] * u[j][0] + g[j][1] * u[j][1] + g[j][2] * u[j][2]);
         r[1] += (double)(g[j][0] * w[j][0] + g[j][1] * w[j][1] + g[j][2] * w[j][2]);
-        // P_v(q) - q' = lam grad V + (q - q')
+        // P_v(q) - q' = mu grad V + (q - q')
         const V4<T> dq = dds[v];
-        wacc[3] += (double)(l.x * (mt * g[j][0] + dq.x) + l.y * (mt * g[j][1] + dq.y) +
-                            l.z * (mt * g[j][2] + dq.z));
+        wacc[3] += (A)l.x * (mu * gd[j][0] + (A)dq.x) + (A)l.y * (mu * gd[j][1] + (A)dq.y) +
+                   (A)l.z * (mu * gd[j][2] + (A)dq.z);
       }
     }
     block_sum<2>(r, red);
@@ -209,8 +284,9 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
     for (int t = base + tid; t < base + nt; t += BLOCK) {
       const int4 id = idn;
       if (t + BLOCK < base + nt) idn = cv.tri_v[t + BLOCK];
-      const V4<T> r0 = reinterpret_cast<const V4<T>*>(cv.tri_rec)[2 * t];
-      const V4<T> r1 = reinterpret_cast<const V4<T>*>(cv.tri_rec)[2 * t + 1];
+      // the element records in FP64 for both state types
+      const V4<A> r0 = reinterpret_cast<const V4<A>*>(cv.tri_rec64)[2 * t];
+      const V4<A> r1 = reinterpret_cast<const V4<A>*>(cv.tri_rec64)[2 * t + 1];
       const A g00 = r0.x, g01 = r0.y, g10 = r0.z, g11 = r0.w, g20 = r1.x, g21 = r1.y;
       const A area = r1.z;
       A fq[3][2], fd[3][2], fl[3][2];  // F(q), F(q - q'), F(lam)
@@ -297,8 +373,8 @@ __global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
     for (int e = base + tid; e < base + ne; e += BLOCK) {
       const int4 id = idn;
       if (e + BLOCK < base + ne) idn = cv.hin_v[e + BLOCK];
-      const V4<T> r0 = reinterpret_cast<const V4<T>*>(cv.hin_rec)[2 * e];
-      const V4<T> r1 = reinterpret_cast<const V4<T>*>(cv.hin_rec)[2 * e + 1];
+      const V4<A> r0 = reinterpret_cast<const V4<A>*>(cv.hin_rec64)[2 * e];
+      const V4<A> r1 = reinterpret_cast<const V4<A>*>(cv.hin_rec64)[2 * e + 1];
       const A k0 = r0.x, k1 = r0.y, k2 = r0.z, k3 = r0.w, ce = r1.x, rr = r1.y;
       A yq[3], yd[3], yl[3];  // y(q), y(q - q'), y(lam)
 #pragma unroll

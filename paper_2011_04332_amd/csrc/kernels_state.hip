@@ -352,4 +352,23 @@ NPFEM_INST(float)
 NPFEM_INST(double)
 #undef NPFEM_INST
 
+// dst = s src (n values)
+template <typename T>
+__global__ void __launch_bounds__(256) scale_kernel(const T* __restrict__ src, T* __restrict__ dst,
+                                                    long long n, double s) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = T(s * (double)src[i]);
+}
+
+template <typename T>
+hipError_t launch_scale(const T* src, T* dst, long long n, double s, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const long long blocks = std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(scale_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, src, dst, n, s);
+  return hipGetLastError();
+}
+template hipError_t launch_scale<float>(const float*, float*, long long, double, hipStream_t);
+template hipError_t launch_scale<double>(const double*, double*, long long, double, hipStream_t);
+
 }  // namespace npfem

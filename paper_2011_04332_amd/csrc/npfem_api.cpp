@@ -78,6 +78,8 @@ struct ClassState {
   void* view_ptrs[19] = {};    // device pointers (see upload_class)
   void* op = nullptr;          // stored global-step operator [Npad][Npad]
   void* op_frag = nullptr;     // 16-bit operator in fragment order (column-stationary kernel)
+  void* op_adj = nullptr;      // non-FP64 batches: FP32 A^-1 - adj_s I (the adjoint's solve)
+  double adj_s = 0.0;
   double beta = 0.0;           // split scale (low precision)
   double kappa = 0.0;          // max row sum of |Ainv - (h^2/m) I| / (h^2/m) (low precision)
   double r_rest = 0.0;         // max distance of a rest vertex from the rest centroid
@@ -251,6 +253,7 @@ struct npfem_batch_s {
       for (void* p : c.dev) hipFree(p);
       if (c.op) hipFree(c.op);
       if (c.op_frag) hipFree(c.op_frag);
+      if (c.op_adj) hipFree(c.op_adj);
     }
     for (void* p : allocs) hipFree(p);
     if (ckpt) hipFree(ckpt);
@@ -336,6 +339,24 @@ int upload_class(ClassState& c) {
   if ((rc = upload_vec(c, tri_rec, &v[1], "tri_rec"))) return rc;
   if ((rc = upload_vec(c, hin_v, &v[2], "hin_v"))) return rc;
   if ((rc = upload_vec(c, hin_rec, &v[3], "hin_rec"))) return rc;
+  if constexpr (sizeof(T) == 8) {
+    v[15] = v[1];
+    v[16] = v[3];
+  } else {
+    std::vector<double> tri64(8 * (size_t)M.F, 0.0), hin64(8 * (size_t)M.E, 0.0);
+    for (int i = 0; i < M.F; ++i) {
+      const int t = tord[i];
+      for (int k = 0; k < 6; ++k) tri64[8 * (size_t)i + k] = M.G[6 * (size_t)t + k];
+      tri64[8 * (size_t)i + 6] = M.area[t];
+    }
+    for (int e = 0; e < M.E; ++e) {
+      for (int r = 0; r < 4; ++r) hin64[8 * (size_t)e + r] = M.K[4 * (size_t)e + r];
+      hin64[8 * (size_t)e + 4] = M.cw[e];
+      hin64[8 * (size_t)e + 5] = M.rr[e];
+    }
+    if ((rc = upload_vec(c, tri64, &v[15], "tri_rec64"))) return rc;
+    if ((rc = upload_vec(c, hin64, &v[16], "hin_rec64"))) return rc;
+  }
   // fixed-width, vertex-major incidence ([N][slot]); entries keep ascending
   // element order, padding contributes zero
   const int N = M.N;
@@ -440,6 +461,8 @@ ClassSlice<T> slice_of(const ClassState& c) {
   v.tri_rec = (const T*)c.view_ptrs[1];
   v.hin_v = (const int4*)c.view_ptrs[2];
   v.hin_rec = (const T*)c.view_ptrs[3];
+  v.tri_rec64 = (const double*)c.view_ptrs[15];
+  v.hin_rec64 = (const double*)c.view_ptrs[16];
   v.DT = c.DT;
   v.DH = c.DH;
   v.vt_tri = (const int*)c.view_ptrs[5];
@@ -664,6 +687,12 @@ int factorise(npfem_batch_s* b, double dt) {
       }
     }
     e = launch_convert_operator(b->gemm_kind, dA, c.Npad, hm, c.beta, c.op, nullptr);
+    // the adjoint's operator for FP32 state: A^-1 without its identity part
+    if (e == hipSuccess && b->gemm_kind != 1) {
+      if (!c.op_adj) e = hipMalloc(&c.op_adj, sizeof(float) * (size_t)c.Npad * c.Npad);
+      c.adj_s = hm;
+      if (e == hipSuccess) e = launch_convert_offdiag(dA, c.Npad, hm, static_cast<float*>(c.op_adj), nullptr);
+    }
     // fragment copy for the column-stationary kernel, where it takes the
     // class (FP32: 48 columns of Npad values in LDS; 16-bit: k-steps <= 24)
     const bool frag = b->gemm_kind == 0 ? (size_t)48 * c.Npad * 4 <= 160 * 1024
@@ -707,7 +736,7 @@ bool sweeps_adaptive(const npfem_batch_s* b) {
 // are batch column buffers.
 template <typename T>
 int enqueue_solve(npfem_batch_s* b, ClassState& c, T* B, T* C, const T* D, double h,
-                  hipStream_t st, bool step_solve) {
+                  hipStream_t st, bool step_solve, T* adj_sb = nullptr) {
   T* res = static_cast<T*>(b->res);
   const T* w = b->per_cell ? static_cast<const T*>(b->weights_dev) : nullptr;
   const bool lp = b->gemm_kind >= 2;
@@ -727,7 +756,22 @@ int enqueue_solve(npfem_batch_s* b, ClassState& c, T* B, T* C, const T* D, doubl
   g.mode = lp ? EPI_SPLIT_SET : EPI_SET;
   g.hm = c.hm_eff(h);
   g.beta = c.beta;
-  NPFEM_TIMED(NPFEM_KERNEL_GLOBAL, launch_gemm(b->gemm_kind, c.gemm_tile, g, st), "global step");
+  if (adj_sb && c.op_adj) {
+    // the adjoint's solve for FP32 state: C = (A^-1 - s I) B + s B with the
+    // FP32 operator that keeps the constraints' coupling to FP32 precision
+    // (adj_sb: workspace for s B)
+    const long long n = 3LL * c.n_cells * c.Npad;
+    HIP_TRY(launch_scale<T>(B + c.elem0, adj_sb + c.elem0, n, c.adj_s, st), "adjoint solve");
+    GemmArgs a = g;
+    a.A = c.op_adj;
+    a.A_frag = nullptr;
+    a.D = adj_sb + c.elem0;
+    a.colscale = nullptr;
+    a.mode = EPI_SET;
+    HIP_TRY(launch_gemm(0, 0, a, st), "adjoint solve");
+  } else {
+    NPFEM_TIMED(NPFEM_KERNEL_GLOBAL, launch_gemm(b->gemm_kind, c.gemm_tile, g, st), "global step");
+  }
   // FP32 state with the automatic sweep count: sweep s + 1 runs for a cell
   // only while the bound rho^(s+1) |delta| on the error left in its delta
   // exceeds the FP32 rounding of the cell's coordinates (2^-24 of its rest
@@ -1183,7 +1227,7 @@ int adjoint_impl(npfem_batch_s* b, const void* dL_dx, const void* dL_dv, void* d
   int rc;
   if ((rc = grow(&b->tape, &b->tape_bytes, sizeof(T) * per_step * ce, "adjoint tape"))) return rc;
   const size_t wbytes = sizeof(double) * 4 * (size_t)b->n_cells;
-  if ((rc = grow(&b->adj_work, &b->adj_work_bytes, sizeof(T) * (4 * sv + 3 * cols) + wbytes + 256,
+  if ((rc = grow(&b->adj_work, &b->adj_work_bytes, sizeof(T) * (4 * sv + 4 * cols) + wbytes + 256,
                  "adjoint workspace")))
     return rc;
   double* wbar = static_cast<double*>(b->adj_work);
@@ -1194,6 +1238,7 @@ int adjoint_impl(npfem_batch_s* b, const void* dL_dx, const void* dL_dv, void* d
   T* lam = vbar + sv;
   T* gbar = lam + cols;
   T* sbar = gbar + cols;
+  T* sgbar = sbar + cols;  // s gbar (the FP32-state solve, enqueue_solve)
   T* tape = static_cast<T*>(b->tape);
   T* ckpt = static_cast<T*>(b->ckpt);
   T* fbar = static_cast<T*>(dL_df);
@@ -1236,7 +1281,9 @@ int adjoint_impl(npfem_batch_s* b, const void* dL_dx, const void* dL_dv, void* d
       for (int k = K - 1; k >= 0; --k) {
         for (auto& c : b->cls) {
           if (c.n_cells == 0) continue;
-          if ((rc = enqueue_solve<T>(b, c, gbar, lam, nullptr, h, st, false))) return rc;
+          if ((rc = enqueue_solve<T>(b, c, gbar, lam, nullptr, h, st, false,
+                                     b->fp64 ? nullptr : sgbar)))
+            return rc;
           AdjArgs<T> a;
           a.cs = slice_of<T>(c);
           a.xn = tj;

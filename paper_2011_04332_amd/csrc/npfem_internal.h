@@ -19,6 +19,10 @@ struct ClassView {
   const T* tri_rec;    // [F][8]: G (3x2 row-major), area, 0
   const int4* hin_v;   // [E] (i, j, k, l)
   const T* hin_rec;    // [E][8]: K[4], c, r_rest, 0, 0
+  // the same records in FP64 (the adjoint's element arithmetic: near rest
+  // the weight gradients move with the rounding of G, area and K)
+  const double* tri_rec64;
+  const double* hin_rec64;
   // Vertex incidence padded to a fixed width, vertex-major ([N][slot]: a
   // thread reads its vertex's entries as one contiguous run, and a wave's
   // runs are contiguous too); entries of a vertex are in ascending element
@@ -266,6 +270,10 @@ hipError_t launch_spd_inverse(double* A, int n, int ld, double* scratch, int* pi
 // the column-stationary kernel does not take the class: then no copy).
 hipError_t launch_convert_fragments(int kind, const void* op, int Npad, void* out, hipStream_t st);
 int gemm_rs_nks(int Npad);
+hipError_t launch_convert_offdiag(const double* Ainv, int Npad, double s, float* out,
+                                  hipStream_t st);
+template <typename T>
+hipError_t launch_scale(const T* src, T* dst, long long n, double s, hipStream_t st);
 hipError_t launch_convert_operator(int kind, const double* Ainv, int Npad, double hm, double beta,
                                    void* out, hipStream_t st);
 hipError_t launch_max_abs_split(const double* Ainv, int n, int Npad, double hm, double* out,
