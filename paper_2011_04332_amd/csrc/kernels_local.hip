@@ -19,8 +19,8 @@
 // vanishes at the fixed point), which also shrinks the absolute error of a
 // 16-bit product.
 //
-// LDS holds the cell's vertices as 16/32-byte records (one vector read per
-// vertex), and the per-element contributions, which each vertex then gathers
+// LDS holds the cell's vertices as 12-byte (FP32) or 32-byte (FP64) records,
+// and the per-element contributions, which each vertex then gathers
 // through fixed-width incidence lists in a fixed order (no atomics): results
 // are bitwise reproducible. Triangles and hinges go through LDS in chunks
 // sized to the budget (a vertex adds its entries chunk by chunk, each chunk's
@@ -47,14 +47,23 @@ struct LocalLaunch {
 // fetched in one memory round trip before the gathers use them.
 // 0: widths read at run time.
 // Occupancy target (waves per SIMD) for FP32, which sets the register
-// budget: with 256 threads the LDS of a 642-vertex cell allows three
-// workgroups per CU (three waves per SIMD); with 128 or 512 threads four
-// waves per SIMD (at most 128 registers) keep the incidence prefetches of
-// two vertices in registers. Six or more vertices per thread means a large
-// mesh whose LDS allows one workgroup per CU: no register cap.
+// budget (at most 128 registers at four): with 12-byte vertex records the
+// LDS of a 642-vertex cell (38.7 KB at 256 threads) lets four workgroups
+// share a CU, four waves per SIMD (16-byte records allowed three). The
+// extra wave hides more of the gathers' latency than the second LDS
+// instruction per 12-byte record read costs. Six or more vertices per
+// thread means a large mesh whose LDS allows one workgroup per CU: no
+// register cap.
 template <typename T, int BLOCK, int VPT>
 constexpr int local_waves_per_eu() {
-  return VPT >= 6 ? 1 : sizeof(T) == 4 ? (BLOCK == 256 ? 3 : 4) : 2;
+  return VPT >= 6 ? 1 : sizeof(T) == 4 ? 4 : 2;
+}
+
+// LDS taken by the q records (N + 1) in doubles, rounded up to 16 bytes so
+// that the work region's vector records stay aligned.
+template <typename T>
+__host__ __device__ constexpr int local_q_doubles(int N) {
+  return ((int)sizeof(typename LocalRec<T>::type) * (N + 1) + 15) / 16 * 2;
 }
 
 template <typename T, int BLOCK, int VPT, int KT, int KH>
@@ -81,11 +90,13 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
   const T* __restrict__ ccol = a.cterm + cb;
   T* __restrict__ rcol = a.rhs + cb;
 
+  typedef typename LocalRec<T>::type Q;
   double* red = smem_local;  // 8 * NW doubles
   // q: N records and a zero record N, which the padding entries of the volume
-  // fan lists point at (their cross product is 0 only for finite records)
-  V4<T>* qs = reinterpret_cast<V4<T>*>(smem_local + 8 * NW);
-  T* work = reinterpret_cast<T*>(qs + N + 1);
+  // fan lists point at (their cross product is 0 only for finite records);
+  // the work region starts at the next 16-byte boundary
+  Q* qs = reinterpret_cast<Q*>(smem_local + 8 * NW);
+  T* work = reinterpret_cast<T*>(smem_local + 8 * NW + local_q_doubles<T>(N));
 
   T ws, wa, wb, wv;
   if (a.weights) {
@@ -110,20 +121,20 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
   // ---- stage q = x + delta (up to six vertex sets per thread: every set's
   // loads in flight at once, VPT * BLOCK >= N, clamped reads) ----
   if constexpr (VPT <= 6) {
-    V4<T> sq[VPT];
+    Q sq[VPT];
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int v = min(tid + j * BLOCK, N - 1);
-      sq[j] = V4<T>{px[v] + dcol[v], py[v] + dcol[Npad + v], pz[v] + dcol[2 * Npad + v], T(0)};
+      sq[j] = make_rec<Q>(px[v] + dcol[v], py[v] + dcol[Npad + v], pz[v] + dcol[2 * Npad + v]);
     }
 #pragma unroll
     for (int j = 0; j < VPT; ++j)
       if (tid + j * BLOCK < N) qs[tid + j * BLOCK] = sq[j];
   } else {
     for (int v = tid; v < N; v += BLOCK)
-      qs[v] = V4<T>{px[v] + dcol[v], py[v] + dcol[Npad + v], pz[v] + dcol[2 * Npad + v], T(0)};
+      qs[v] = make_rec<Q>(px[v] + dcol[v], py[v] + dcol[Npad + v], pz[v] + dcol[2 * Npad + v]);
   }
-  if (tid == 0) qs[N] = V4<T>{T(0), T(0), T(0), T(0)};
+  if (tid == 0) qs[N] = make_rec<Q>(T(0), T(0), T(0));
   __syncthreads();
 
   T acc[VPT][3];
@@ -137,7 +148,7 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
   // passes run after the triangle phase (they need the work region). ----
   T g[VPT][3];
   double vs[3], vmq;
-  volume_pass_local<T, BLOCK, VPT, KT>(cv, qs, qs, true, g, vs, vmq, ring);
+  volume_pass_local<T, BLOCK, VPT, KT, Q>(cv, qs, qs, true, g, vs, vmq, ring);
   block_sum_max_write<3, true>(vs, vmq, red, 0);
   bool vol_pending = true, vol_conv = false;
   double lam = 0.0;
@@ -161,7 +172,7 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
       }
       const T g00 = r0.x, g01 = r0.y, g10 = r0.z, g11 = r0.w, g20 = r1.x, g21 = r1.y;
       const T area = r1.z;
-      const V4<T> qa = qs[id.x], qb = qs[id.y], qc = qs[id.z];
+      const Q qa = qs[id.x], qb = qs[id.y], qc = qs[id.z];
       // F from the edge vectors (the rows of G sum to zero): exactly
       // translation-invariant with the rounded G, and the differences of
       // nearby coordinates are exact, so F carries the rounding of O(1)
@@ -279,7 +290,7 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
     int ring2[VPT][KT > 0 ? KT : 1];
     if constexpr (KT > 0) ring_indices<T, BLOCK, VPT, KT>(cv, ring2);
     T p[VPT][3];
-    lam = volume_continue<T, BLOCK, VPT, false, KT>(cv, qs, reinterpret_cast<V4<T>*>(work), red,
+    lam = volume_continue<T, BLOCK, VPT, false, KT, Q>(cv, qs, reinterpret_cast<Q*>(work), red,
                                                     g, p, lam, vol_conv, 1, a.max_vol_iter,
                                                     a.vol_tol, a.vol_abs, bad, ring2);
   }
@@ -316,7 +327,7 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
       if (v < N && k1 > k0) {
-        const V4<T> q = qs[v];
+        const Q q = qs[v];
         T best = T(0);
         int kb = k0;
         for (int k = k0; k < k1; ++k) {
@@ -369,7 +380,7 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
         r1n = hrec[2 * (e + BLOCK) + 1];
       }
       const T k0 = r0.x, k1 = r0.y, k2 = r0.z, k3 = r0.w, ce = r1.x, rr = r1.y;
-      const V4<T> qi = qs[id.x], qj = qs[id.y], qk = qs[id.z], ql = qs[id.w];
+      const Q qi = qs[id.x], qj = qs[id.y], qk = qs[id.z], ql = qs[id.w];
       // y from the differences to q_i (the stencil weights sum to zero), as F
       (void)k0;
       T yq[3];
@@ -497,14 +508,16 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
   if (__syncthreads_or(bad) && tid == 0) atomicOr(a.status, ST_NONFINITE);
 }
 
-// LDS: reductions, q as 4-component records (plus a zero record), and a work region that
-// holds the volume iterate p (N records plus a zero record) or one chunk of
-// triangle (6 values) or hinge (4 values) contributions.
+// LDS: reductions, q as vertex records (plus a zero record; 12 or 32 bytes,
+// the region rounded up to 16 bytes), and a work region that holds the
+// volume iterate p (N records plus a zero record) or one chunk of triangle
+// (6 values) or hinge (4 values) contributions.
 template <typename T>
 size_t local_smem_bytes_chunks(const ClassView<T>& cv, int block, int* tch, int* hch) {
-  const size_t fixed = 8 * sizeof(double) * (block / kWave) + sizeof(T) * 4 * ((size_t)cv.N + 1);
+  const size_t fixed = 8 * sizeof(double) * (block / kWave) + sizeof(double) * local_q_doubles<T>(cv.N);
   const size_t max_total = 160 * 1024;
-  const size_t work_min = 4 * ((size_t)cv.N + 1);
+  // the volume iterate's N + 1 records, in elements of T
+  const size_t work_min = sizeof(typename LocalRec<T>::type) / sizeof(T) * ((size_t)cv.N + 1);
   const size_t want = std::max<size_t>(6 * (size_t)cv.F, 4 * (size_t)cv.E);
   const size_t avail = max_total > fixed ? (max_total - fixed) / sizeof(T) : 0;
   // cap the chunk budget so that small meshes leave room for several

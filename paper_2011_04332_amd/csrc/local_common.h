@@ -17,9 +17,40 @@ struct alignas(2 * sizeof(T)) V2 {
   T x, y;
 };
 
+// Three-component record (12 bytes in FP32): the local step's LDS vertex
+// records, so that a 642-vertex cell's step fits four workgroups per CU.
+template <typename T>
+struct alignas(sizeof(T)) V3 {
+  T x, y, z;
+};
+
 template <typename T>
 __device__ __forceinline__ T comp(const V4<T>& v, int d) {
   return d == 0 ? v.x : (d == 1 ? v.y : v.z);
+}
+template <typename T>
+__device__ __forceinline__ T comp(const V3<T>& v, int d) {
+  return d == 0 ? v.x : (d == 1 ? v.y : v.z);
+}
+
+// Record of the local step's LDS vertex arrays: 12 bytes in FP32, a
+// 32-byte vector record in FP64.
+template <typename T>
+struct LocalRec {
+  typedef V4<T> type;
+};
+template <>
+struct LocalRec<float> {
+  typedef V3<float> type;
+};
+
+template <typename R>
+__device__ __forceinline__ R make_rec(decltype(R::x) x, decltype(R::x) y, decltype(R::x) z) {
+  R r{};
+  r.x = x;
+  r.y = y;
+  r.z = z;
+  return r;
 }
 
 // grad_v V(p) = (1/6) sum over the fan of v of p_b x p_c, (v, b, c)
@@ -27,15 +58,15 @@ __device__ __forceinline__ T comp(const V4<T>& v, int d) {
 // exact zero cross product whatever the record holds). KT > 0 fixes the fan
 // width at compile time (it must equal cv.DT): all indices are fetched in
 // one round trip before any is used. KT = 0 reads cv.DT, 8 entries a time.
-template <typename T, int KT>
-__device__ __forceinline__ void volume_gradient(const ClassView<T>& cv, const V4<T>* ps, int v,
+template <typename T, int KT, typename R>
+__device__ __forceinline__ void volume_gradient(const ClassView<T>& cv, const R* ps, int v,
                                                 T& gx, T& gy, T& gz) {
   const int N = cv.N;
   gx = gy = gz = T(0);
   const int* __restrict__ fix = cv.vt_fan + v * (KT > 0 ? KT : cv.DT);
   auto add = [&](int bc) {
-    const V4<T> pb = ps[bc & 0xffff];
-    const V4<T> pc = ps[bc >> 16];
+    const R pb = ps[bc & 0xffff];
+    const R pc = ps[bc >> 16];
     gx += pb.y * pc.z - pb.z * pc.y;
     gy += pb.z * pc.x - pb.x * pc.z;
     gz += pb.x * pc.y - pb.y * pc.x;
@@ -67,17 +98,17 @@ __device__ __forceinline__ void volume_gradient(const ClassView<T>& cv, const V4
 // The same sum from the one-ring n_0 .. n_{KT-1} (indices in registers; a
 // ring shorter than KT is padded with n_0, whose terms n_0 x n_0 vanish):
 // (1/6) sum_k n_k x n_{k+1 mod KT}, one LDS record per neighbour.
-template <typename T, int KT>
-__device__ __forceinline__ void volume_gradient_ring(const V4<T>* ps, const int (&r)[KT], T& gx,
+template <typename T, int KT, typename R>
+__device__ __forceinline__ void volume_gradient_ring(const R* ps, const int (&r)[KT], T& gx,
                                                      T& gy, T& gz) {
-  V4<T> p[KT];
+  R p[KT];
 #pragma unroll
   for (int u = 0; u < KT; ++u) p[u] = ps[r[u]];
   gx = gy = gz = T(0);
 #pragma unroll
   for (int u = 0; u < KT; ++u) {
-    const V4<T>& pb = p[u];
-    const V4<T>& pc = p[(u + 1) % KT];
+    const R& pb = p[u];
+    const R& pc = p[(u + 1) % KT];
     gx += pb.y * pc.z - pb.z * pc.y;
     gy += pb.z * pc.x - pb.x * pc.z;
     gz += pb.x * pc.y - pb.y * pc.x;
@@ -124,9 +155,9 @@ __device__ __forceinline__ void ring_indices(const ClassView<T>& cv, int (&ring)
 // One pass's per-thread part: the gradient g at src (q itself on the first
 // pass) for this thread's vertices and its partial sums s[0] = p.g,
 // s[1] = |g|^2, s[2] = g.(q - p) (later passes) and mq = max |q|^2 (first).
-template <typename T, int BLOCK, int VPT, int KT>
-__device__ __forceinline__ void volume_pass_local(const ClassView<T>& cv, const V4<T>* qs,
-                                                  const V4<T>* src, bool first,
+template <typename T, int BLOCK, int VPT, int KT, typename R>
+__device__ __forceinline__ void volume_pass_local(const ClassView<T>& cv, const R* qs,
+                                                  const R* src, bool first,
                                                   T (&g)[VPT][3], double (&s)[3], double& mq,
                                                   const int (&fan)[VPT][KT > 0 ? KT : 1]) {
   const int N = cv.N, tid = threadIdx.x;
@@ -141,13 +172,13 @@ __device__ __forceinline__ void volume_pass_local(const ClassView<T>& cv, const 
       if constexpr (KT > 0) {
         volume_gradient_ring<T, KT>(src, fan[j], gx, gy, gz);
       } else {
-        volume_gradient<T, 0>(cv, src, v, gx, gy, gz);
+        volume_gradient<T, 0, R>(cv, src, v, gx, gy, gz);
       }
       g[j][0] = gx;
       g[j][1] = gy;
       g[j][2] = gz;
-      const V4<T> q = qs[v];
-      const V4<T> p = first ? q : src[v];
+      const R q = qs[v];
+      const R p = first ? q : src[v];
       s[0] += (double)(p.x * gx + p.y * gy + p.z * gz);
       s[1] += (double)(gx * gx + gy * gy + gz * gz);
       if (!first) s[2] += (double)(gx * (q.x - p.x) + gy * (q.y - p.y) + gz * (q.z - p.z));
@@ -183,8 +214,8 @@ __device__ __forceinline__ double volume_lambda(const ClassView<T>& cv, const do
 // p = q + lam g, take the gradient there, and so on (see volume_project).
 // Uses red halves (pass & 1); ps needs N + 1 records. Call from uniform
 // control flow.
-template <typename T, int BLOCK, int VPT, bool STORE_P, int KT>
-__device__ double volume_continue(const ClassView<T>& cv, const V4<T>* qs, V4<T>* ps,
+template <typename T, int BLOCK, int VPT, bool STORE_P, int KT, typename R>
+__device__ double volume_continue(const ClassView<T>& cv, const R* qs, R* ps,
                                   double* red, T (&g)[VPT][3], T (&pv)[VPT][3], double lam,
                                   bool conv, int done, int max_it, double vol_tol,
                                   double vol_abs, int& bad,
@@ -199,18 +230,18 @@ __device__ double volume_continue(const ClassView<T>& cv, const V4<T>* qs, V4<T>
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int v = tid + j * BLOCK;
-      const V4<T> q = v < N ? qs[v] : V4<T>{T(0), T(0), T(0), T(0)};
+      const R q = v < N ? qs[v] : make_rec<R>(T(0), T(0), T(0));
       pv[j][0] = q.x + lt * g[j][0];
       pv[j][1] = q.y + lt * g[j][1];
       pv[j][2] = q.z + lt * g[j][2];
-      if (v < N) ps[v] = V4<T>{pv[j][0], pv[j][1], pv[j][2], T(0)};
+      if (v < N) ps[v] = make_rec<R>(pv[j][0], pv[j][1], pv[j][2]);
     }
-    if (!stored && tid == 0) ps[N] = V4<T>{T(0), T(0), T(0), T(0)};
+    if (!stored && tid == 0) ps[N] = make_rec<R>(T(0), T(0), T(0));
     stored = true;
     __syncthreads();
     if (last) break;
     double s[3], mq;
-    volume_pass_local<T, BLOCK, VPT, KT>(cv, qs, ps, false, g, s, mq, fan);
+    volume_pass_local<T, BLOCK, VPT, KT, R>(cv, qs, ps, false, g, s, mq, fan);
     // one barrier; afterwards every read of ps in this pass is done
     block_sum_max<3, false>(s, mq, red, it & 1);
     lam = volume_lambda<T>(cv, s, mq, it, lam, vol_tol, vol_abs, bad, conv);
@@ -218,17 +249,17 @@ __device__ double volume_continue(const ClassView<T>& cv, const V4<T>* qs, V4<T>
   return lam;
 }
 
-template <typename T, int BLOCK, int VPT, bool STORE_P, int KT = 0>
-__device__ double volume_project(const ClassView<T>& cv, const V4<T>* qs, V4<T>* ps, double* red,
+template <typename T, int BLOCK, int VPT, bool STORE_P, int KT = 0, typename R = V4<T>>
+__device__ double volume_project(const ClassView<T>& cv, const R* qs, R* ps, double* red,
                                  T (&g)[VPT][3], T (&pv)[VPT][3], int max_it, double vol_tol,
                                  double vol_abs, int& bad,
                                  const int (&fan)[VPT][KT > 0 ? KT : 1]) {
   double s[3], mq;
-  volume_pass_local<T, BLOCK, VPT, KT>(cv, qs, qs, true, g, s, mq, fan);
+  volume_pass_local<T, BLOCK, VPT, KT, R>(cv, qs, qs, true, g, s, mq, fan);
   block_sum_max<3, true>(s, mq, red, 0);
   bool conv;
   const double lam = volume_lambda<T>(cv, s, mq, 0, 0.0, vol_tol, vol_abs, bad, conv);
-  return volume_continue<T, BLOCK, VPT, STORE_P, KT>(cv, qs, ps, red, g, pv, lam, conv, 1, max_it,
+  return volume_continue<T, BLOCK, VPT, STORE_P, KT, R>(cv, qs, ps, red, g, pv, lam, conv, 1, max_it,
                                                      vol_tol, vol_abs, bad, fan);
 }
 
