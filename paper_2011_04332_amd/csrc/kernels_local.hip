@@ -51,12 +51,14 @@ struct LocalLaunch {
 // LDS of a 642-vertex cell (38.7 KB at 256 threads) lets four workgroups
 // share a CU, four waves per SIMD (16-byte records allowed three). The
 // extra wave hides more of the gathers' latency than the second LDS
-// instruction per 12-byte record read costs. Six or more vertices per
-// thread means a large mesh whose LDS allows one workgroup per CU: no
-// register cap.
+// instruction per 12-byte record read costs. Four vertices per thread
+// (meshes of up to 1024 vertices) take three: their LDS leaves room for
+// fewer workgroups, and at 128 registers they would spill. Six or more
+// vertices per thread means a large mesh whose LDS allows one workgroup per
+// CU: no register cap.
 template <typename T, int BLOCK, int VPT>
 constexpr int local_waves_per_eu() {
-  return VPT >= 6 ? 1 : sizeof(T) == 4 ? 4 : 2;
+  return VPT >= 6 ? 1 : sizeof(T) == 4 ? (VPT <= 3 ? 4 : 3) : 2;
 }
 
 // LDS taken by the q records (N + 1) in doubles, rounded up to 16 bytes so
@@ -358,7 +360,11 @@ __global__ void __launch_bounds__(BLOCK, (local_waves_per_eu<T, BLOCK, VPT>()))
   T ct[VPT][3];
 #pragma unroll
   for (int j = 0; j < VPT; ++j) {
-    const int v = min(tid + j * BLOCK, N - 1);  // (rows past N are not stored)
+    int v = min(tid + j * BLOCK, N - 1);  // (rows past N are not stored)
+    // an opaque copy of the index: the addresses are formed here again
+    // instead of the staging's 64-bit addresses staying live through the
+    // triangle phase (at the four-wave register budget they were spilled)
+    asm volatile("" : "+v"(v));
 #pragma unroll
     for (int d = 0; d < 3; ++d) ct[j][d] = ccol[d * Npad + v] - mh2 * dcol[d * Npad + v];
   }
