@@ -14,6 +14,8 @@
 // Tiling: 256 threads = 4 waves in a 2x2 grid, each wave owns a
 // (BM/2) x (BN/2) block of 16x16 accumulators; K advances BK rows at a time
 // through double-buffered LDS tiles with register prefetch.
+#include <algorithm>
+
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
@@ -390,7 +392,10 @@ __global__ void __launch_bounds__(256) gemm_lp_kernel(GemmArgs g) {
 // it) in 16-row blocks straight into MFMA operand registers, ahead of its use.
 // 12288 columns make 256 workgroups, one per CU, so there is no tile
 // quantisation; the four waves split the row blocks, and the row blocks left
-// over after an even split are split by column group.
+// over after an even split are split by column group. With fewer column
+// blocks than CUs (FP32, small batches) the row blocks are further split over
+// up to four workgroups per column block (gridDim.y), each staging the whole
+// column block, so that the product still spreads over the chip.
 //
 // LDS layout: k-chunks of 4 (FP32) or 8 (16-bit) values of each column are
 // contiguous 16-byte records, chunk-major: record (q, n) at q * RS_BN + n.
@@ -598,8 +603,12 @@ __global__ void __launch_bounds__(256) gemm_rs_f32_kernel(GemmArgs g) {
   const int rot = full > 0 ? 2 * ((blockIdx.x / 8) % (full / 2)) : 0;
   // C = D + product (D = C when accumulating, none if null)
   const float* Dadd = g.mode == EPI_ADD ? C : static_cast<const float*>(g.D);
+  // rows split over gridDim.y workgroups per column block (few columns):
+  // part s takes the row pairs and leftover units s, s + parts, ...
+  const int s = blockIdx.y, parts = gridDim.y;
   auto pairs = [&](auto nit) {
-    for (int i = 2 * wave; i < full; i += 8) {
+    for (int p = s + parts * wave; 2 * p < full; p += 4 * parts) {
+      const int i = 2 * p;
       const int rb = i + rot < full ? i + rot : i + rot - full;
       rs_rows_f32<2, RS_NG, decltype(nit)::value>(A, rs_lds, Npad, rb, 0, C, n0, ncols, Dadd, g,
                                                   lane);
@@ -614,7 +623,7 @@ __global__ void __launch_bounds__(256) gemm_rs_f32_kernel(GemmArgs g) {
     case 6: pairs(std::integral_constant<int, 6>{}); break;
     default: pairs(std::integral_constant<int, -1>{}); break;
   }
-  for (int u = wave; u < (nrb - full) * RS_NG; u += 4)
+  for (int u = s + parts * wave; u < (nrb - full) * RS_NG; u += 4 * parts)
     rs_rows_f32<1, 1>(A, rs_lds, Npad, full + u / RS_NG, u % RS_NG, C, n0, ncols, Dadd, g,
                       lane);
 }
@@ -872,6 +881,21 @@ hipError_t gemm_prepare(int kind, int tile, int npad) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
 }
 
+// Compute units of the current device (queried once per device).
+static int device_cu_count() {
+  static int cached[16] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+      n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
 static hipError_t run_gemm_rs(int kind, const GemmArgs& g, hipStream_t st) {
   const size_t smem = rs_lds_bytes(kind, g.Npad);
   const void* fn = rs_kernel(kind, g.Npad);
@@ -880,7 +904,14 @@ static hipError_t run_gemm_rs(int kind, const GemmArgs& g, hipStream_t st) {
   GemmArgs a = g;
   void* args[] = {&a};
   const int blocks = (g.ncols + RS_NG * 16 - 1) / (RS_NG * 16);
-  return hipLaunchKernel(fn, dim3(blocks), dim3(256), args, smem, st);
+  // FP32 with fewer column blocks than CUs: the rows are split over up to
+  // four workgroups per column block (each stages the whole column block)
+  int parts = 1;
+  if (kind == 0) {
+    const int cus = device_cu_count();
+    parts = std::max(1, std::min(4, cus / std::max(blocks, 1)));
+  }
+  return hipLaunchKernel(fn, dim3(blocks, parts), dim3(256), args, smem, st);
 }
 
 // ---------------------------------------------------------------- dispatch
