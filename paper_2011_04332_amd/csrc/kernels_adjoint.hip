@@ -51,8 +51,19 @@ __device__ __forceinline__ void cross_acc(const V4<T>& a, const V4<T>& b, T (&o)
   o[2] += a.x * b.y - a.y * b.x;
 }
 
+// Register budget: a 642-vertex cell's FP32 adjoint step (512 threads, two
+// vertices per thread, 62 KB of LDS) leaves LDS for two workgroups per CU,
+// which needs at most 128 registers (four waves per SIMD); uncapped it took
+// 150 and ran one workgroup per CU. At the cap a few values spill (80 bytes
+// per thread), and the backward pass is still 10 % faster.
 template <typename T, int BLOCK, int VPT>
-__global__ void __launch_bounds__(BLOCK) adjoint_local_kernel(AdjLaunch<T> L) {
+constexpr int adjoint_waves_per_eu() {
+  return sizeof(T) == 4 && BLOCK == 512 && VPT <= 2 ? 4 : 1;
+}
+
+template <typename T, int BLOCK, int VPT>
+__global__ void __launch_bounds__(BLOCK, (adjoint_waves_per_eu<T, BLOCK, VPT>()))
+    adjoint_local_kernel(AdjLaunch<T> L) {
   extern __shared__ double smem_adj[];
   constexpr int NW = BLOCK / kWave;
   // Element arithmetic (projections, their VJPs and the weight-gradient

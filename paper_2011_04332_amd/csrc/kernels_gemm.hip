@@ -395,7 +395,8 @@ __global__ void __launch_bounds__(256) gemm_lp_kernel(GemmArgs g) {
 // over after an even split are split by column group. With fewer column
 // blocks than CUs (FP32, small batches) the row blocks are further split over
 // up to four workgroups per column block (gridDim.y), each staging the whole
-// column block, so that the product still spreads over the chip.
+// column block, so that the product still spreads over the chip (while every
+// part keeps at least one row pair per wave).
 //
 // LDS layout: k-chunks of 4 (FP32) or 8 (16-bit) values of each column are
 // contiguous 16-byte records, chunk-major: record (q, n) at q * RS_BN + n.
@@ -905,11 +906,13 @@ static hipError_t run_gemm_rs(int kind, const GemmArgs& g, hipStream_t st) {
   void* args[] = {&a};
   const int blocks = (g.ncols + RS_NG * 16 - 1) / (RS_NG * 16);
   // FP32 with fewer column blocks than CUs: the rows are split over up to
-  // four workgroups per column block (each stages the whole column block)
+  // four workgroups per column block (each stages the whole column block),
+  // as long as every part keeps a row pair per wave
   int parts = 1;
   if (kind == 0) {
     const int cus = device_cu_count();
-    parts = std::max(1, std::min(4, cus / std::max(blocks, 1)));
+    const int pairs = (g.Npad / 16 & ~7) / 2;
+    parts = std::max(1, std::min({4, cus / std::max(blocks, 1), pairs / 4}));
   }
   return hipLaunchKernel(fn, dim3(blocks, parts), dim3(256), args, smem, st);
 }

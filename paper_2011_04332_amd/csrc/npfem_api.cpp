@@ -1439,11 +1439,12 @@ int npfem_create_batch(const npfem_mesh* meshes, int32_t n_meshes, const int32_t
     c.elem0 = elem;
     c.vert0 = vert;
     c.local_block = default_local_block(c.N);
-    // default product (the autotuner may pick another): FP32 classes whose 48
-    // columns fit the LDS take the column-stationary kernel (it splits the
-    // rows over several workgroups when the columns are few), else 128 x 128
-    // tiles from 1024 columns on, 64 x 64 below
-    const bool rs_fp32 = b->gemm_kind == 0 && c.Npad % 16 == 0 && (size_t)48 * c.Npad * 4 <= 160 * 1024;
+    // default product (the autotuner may pick another): FP32 classes of 512
+    // to 853 rows (48 columns fit the LDS) take the column-stationary kernel
+    // (it splits the rows over several workgroups when the columns are few),
+    // else 128 x 128 tiles from 1024 columns on, 64 x 64 below
+    const bool rs_fp32 = b->gemm_kind == 0 && c.Npad % 16 == 0 && c.Npad >= 512 &&
+                         (size_t)48 * c.Npad * 4 <= 160 * 1024;
     c.gemm_tile = (3LL * n >= 1024) ? (rs_fp32 ? gemm_num_tiles(0) - 1 : 3) : 0;
     if (n > 0 && c.N > kLocalMaxBlock * kLocalMaxVertsPerThread)
       return fail(NPFEM_ERR_INVALID_ARG,
