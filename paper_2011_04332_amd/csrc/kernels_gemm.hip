@@ -404,7 +404,7 @@ __global__ void __launch_bounds__(256) gemm_lp_kernel(GemmArgs g) {
 // contiguous bytes), so a wave's fetch touches every bank once per 256 bytes.
 constexpr int RS_NG = 3;
 constexpr int RS_BN = RS_NG * 16;
-constexpr int kNumTilesTiled = 13;  // tile ids below are tiled shapes, this one column-stationary
+constexpr int kNumTilesTiled = 14;  // tile ids below are tiled shapes, this one column-stationary
 
 __host__ __device__ inline int rs_k32(int npad) { return (npad + 31) / 32 * 32; }
 
@@ -925,7 +925,7 @@ struct TileShape {
 // RS_NG * 16 columns per workgroup (FP32 and 16-bit only).
 static const TileShape kTiles[] = {{64, 64},  {64, 128}, {128, 64}, {128, 128}, {96, 64},
                                    {96, 128}, {224, 32}, {224, 64}, {96, 96},   {224, 96},
-                                   {224, 128}, {64, 96}, {128, 96}, {0, RS_NG * 16}};
+                                   {224, 128}, {64, 96}, {128, 96}, {64, 32},  {0, RS_NG * 16}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 int gemm_num_tiles(int) { return kNumTiles; }
@@ -977,6 +977,7 @@ hipError_t launch_gemm(int kind, int tile, const GemmArgs& g, hipStream_t st) {
     case 10: return run_kind<224, 128>(kind, g, st);
     case 11: return run_kind<64, 96>(kind, g, st);
     case 12: return run_kind<128, 96>(kind, g, st);
+    case 13: return run_kind<64, 32>(kind, g, st);
     case kNumTilesTiled: return run_gemm_rs(kind, g, st);
     default: return hipErrorInvalidValue;
   }

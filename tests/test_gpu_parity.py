@@ -152,10 +152,11 @@ def test_mixed_precision_uneven_adaptive(prec):
         assert err <= TOL[prec]
 
 
-# every global-step kernel shape (13 tiled shapes, then the column-stationary
+# every global-step kernel shape (14 tiled shapes, then the column-stationary
 # kernel, reported with tile rows 0), forced through set_config
 GEMM_SHAPES = [(64, 64), (64, 128), (128, 64), (128, 128), (96, 64), (96, 128), (224, 32),
-               (224, 64), (96, 96), (224, 96), (224, 128), (64, 96), (128, 96), (0, 48)]
+               (224, 64), (96, 96), (224, 96), (224, 128), (64, 96), (128, 96), (64, 32),
+               (0, 48)]
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
