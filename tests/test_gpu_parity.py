@@ -84,6 +84,31 @@ def test_rbc_lattice_full_size_sampled():
     assert err <= TOL["fp32"]
 
 
+@pytest.mark.parametrize("n_cells", [1024, 2048])
+def test_fp32_product_rows_split_stiff(n_cells):
+    """The FP32 default product for few columns: 1024 (2048) RBCs make 64
+    (128) column blocks of 48, so the column-stationary kernel splits the row
+    pairs over 4 (2) workgroups per block. Stiff twin (the product shapes the
+    positions), 3 steps x 2 PD iterations, 3 sampled cells against the oracle."""
+    from paper_2011_04332_amd import solver
+    import torch
+    s = as_precision(W.stiff(W.rbc_lattice(n_cells=n_cells, n_steps=3, n_iter=2)), np.float32)
+    log(f"fp32 row-split product, {n_cells} RBCs, stiff")
+    b, pos, vel, f, _ = solver.batch_from_suspension(s, precision="fp32")
+    for _ in range(s.n_steps):
+        b.step(f, s.dt, s.n_iter)
+    b.sync_status()
+    torch.cuda.synchronize()
+    cfg = b.config(0)
+    x = pos.double().cpu().numpy()
+    b.close()
+    assert tuple(cfg[1:3]) == (0, 48), cfg  # the column-stationary kernel by default
+    cells = [0, n_cells // 2 + 5, n_cells - 1]
+    err = max_error(s, x, oracle_cells(s, cells))
+    log(f"row-split product {n_cells} err {err:.3e}")
+    assert err <= TOL["fp32"]
+
+
 @pytest.mark.parametrize("stiff", [False, True])
 def test_uneven_batch_per_cell_weights(stiff):
     """RBC + platelet + large-cell classes with per-cell weights (+-20 %)."""
