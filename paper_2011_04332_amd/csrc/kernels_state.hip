@@ -16,6 +16,10 @@ namespace npfem {
 //   cterm  = (m/h^2)(s - x) = (m/h) v + f   (constant over the PD iterations)
 //   delta0 = (s - x)/(1 + alpha h)          (q^0 = s; with mass-proportional
 //            damping alpha the minimiser of the inertia and damping terms)
+// Rows per thread in predict and update (a 656-row RBC column in one pass
+// of 256 threads).
+constexpr int kStateRows = 3;
+
 template <typename T>
 __global__ void __launch_bounds__(256) predict_kernel(ClassSlice<T> cs, const T* __restrict__ pos,
                                                       const T* __restrict__ vel,
@@ -29,21 +33,36 @@ __global__ void __launch_bounds__(256) predict_kernel(ClassSlice<T> cs, const T*
   const double m = (double)cs.mass;
   const double mh = m / h, hm = h * h / m, ds = 1.0 / (1.0 + alpha * h);
   int bad = 0;
-  for (int v = threadIdx.x; v < Npad; v += blockDim.x) {
+  // kStateRows rows per thread with all their loads in flight (clamped
+  // addresses; rows past N are written as zeros)
+  for (int v0 = threadIdx.x; v0 < Npad; v0 += kStateRows * blockDim.x) {
+    T x[kStateRows][3], u[kStateRows][3], f[kStateRows][3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      T c = T(0), dl = T(0);
-      if (v < N) {
-        const T x = pos[d * sumN + vb + v];
-        const T u = vel[d * sumN + vb + v];
-        const T f = force[d * sumN + vb + v];
-        bad |= !(isfinite(x) && isfinite(u) && isfinite(f));
-        const double cd = mh * (double)u + (double)f;
-        c = T(cd);
-        dl = T((h * (double)u + hm * (double)f) * ds);
+    for (int r = 0; r < kStateRows; ++r) {
+      const int v = min(v0 + r * (int)blockDim.x, N - 1);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        x[r][d] = pos[d * sumN + vb + v];
+        u[r][d] = vel[d * sumN + vb + v];
+        f[r][d] = force[d * sumN + vb + v];
       }
-      cterm[cb + d * Npad + v] = c;
-      delta[cb + d * Npad + v] = dl;
+    }
+#pragma unroll
+    for (int r = 0; r < kStateRows; ++r) {
+      const int v = v0 + r * (int)blockDim.x;
+      if (v >= Npad) break;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        T c = T(0), dl = T(0);
+        if (v < N) {
+          bad |= !(isfinite(x[r][d]) && isfinite(u[r][d]) && isfinite(f[r][d]));
+          const double cd = mh * (double)u[r][d] + (double)f[r][d];
+          c = T(cd);
+          dl = T((h * (double)u[r][d] + hm * (double)f[r][d]) * ds);
+        }
+        cterm[cb + d * Npad + v] = c;
+        delta[cb + d * Npad + v] = dl;
+      }
     }
   }
   if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(status, ST_NONFINITE);
@@ -59,12 +78,26 @@ __global__ void __launch_bounds__(256) update_kernel(ClassSlice<T> cs, T* __rest
   const long long vb = cs.vert0 + (long long)lc * N;
   const long long cb = cs.elem0 + 3LL * lc * Npad;
   const double ih = 1.0 / h;
-  for (int v = threadIdx.x; v < N; v += blockDim.x) {
+  for (int v0 = threadIdx.x; v0 < N; v0 += kStateRows * blockDim.x) {
+    T dl[kStateRows][3], x[kStateRows][3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const T dl = delta[cb + d * Npad + v];
-      pos[d * sumN + vb + v] += dl;
-      vel[d * sumN + vb + v] = T((double)dl * ih);
+    for (int r = 0; r < kStateRows; ++r) {
+      const int v = min(v0 + r * (int)blockDim.x, N - 1);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        dl[r][d] = delta[cb + d * Npad + v];
+        x[r][d] = pos[d * sumN + vb + v];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kStateRows; ++r) {
+      const int v = v0 + r * (int)blockDim.x;
+      if (v >= N) break;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        pos[d * sumN + vb + v] = x[r][d] + dl[r][d];
+        vel[d * sumN + vb + v] = T((double)dl[r][d] * ih);
+      }
     }
   }
 }
