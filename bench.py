@@ -244,7 +244,7 @@ def kernel_source_digest():
     h = hashlib.sha256()
     root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2011_04332_amd", "csrc")
     for name in ("kernels_local.hip", "local_common.h", "projections.h", "kernels_gemm.hip",
-                 "device_utils.h", "npfem_internal.h"):
+                 "kernels_state.hip", "device_utils.h", "npfem_internal.h"):
         with open(os.path.join(root, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
