@@ -569,12 +569,25 @@ static LocalFn<T> pick_vpt(int N, int DT, int DH, bool ring) {
   return nullptr;
 }
 
+// 1024 threads (FP32, up to three vertices per thread): a large mesh whose
+// LDS allows one workgroup per CU gets four waves per SIMD instead of two.
+template <typename T>
+static LocalFn<T> pick_1024(int N, int DT, int DH, bool ring) {
+  if constexpr (sizeof(T) == 4) {
+    const int vpt = (N + 1023) / 1024;
+    if (vpt <= 2) return pick_widths<T, 1024, 2>(DT, DH, ring);
+    if (vpt <= 3) return pick_widths<T, 1024, 3>(DT, DH, ring);
+  }
+  return nullptr;
+}
+
 template <typename T>
 static LocalFn<T> pick_local(const ClassView<T>& cv, int block) {
   switch (block) {
     case 128: return pick_vpt<T, 128>(cv.N, cv.DT, cv.DH, cv.vt_ring != nullptr);
     case 256: return pick_vpt<T, 256>(cv.N, cv.DT, cv.DH, cv.vt_ring != nullptr);
     case 512: return pick_vpt<T, 512>(cv.N, cv.DT, cv.DH, cv.vt_ring != nullptr);
+    case 1024: return pick_1024<T>(cv.N, cv.DT, cv.DH, cv.vt_ring != nullptr);
     default: return nullptr;
   }
 }

@@ -1182,6 +1182,9 @@ int autotune(npfem_batch_s* b, double h) {
     a.max_vol_iter = b->max_vol_iter;
     set_volume_tolerances(a, c, b->fp64);
     best = 1e30f;
+    // (1024 threads is left to set_config: it wins for a large mesh alone,
+    // but its 16-wave workgroups wait longer for a free CU beside other
+    // classes' branches, and the trials here time each class alone)
     for (int block : {128, 256, 512}) {
       if (local_prepare<T>(a.cs.cv, block) != hipSuccess) continue;
       float ms = 0.f;
@@ -1938,10 +1941,13 @@ int npfem_set_batch_config(npfem_batch b, int32_t cls, const int32_t in[4]) {
   if (!in || cls < 0 || cls >= (int)b->cls.size())
     return fail(NPFEM_ERR_INVALID_ARG, "class index out of range");
   ClassState& c = b->cls[cls];
-  if (in[0] != 128 && in[0] != 256 && in[0] != 512)
-    return fail(NPFEM_ERR_INVALID_ARG, "local workgroup size must be 128, 256 or 512");
+  if (in[0] != 128 && in[0] != 256 && in[0] != 512 && in[0] != 1024)
+    return fail(NPFEM_ERR_INVALID_ARG, "local workgroup size must be 128, 256, 512 or 1024");
   if ((c.N + in[0] - 1) / in[0] > 11)
     return fail(NPFEM_ERR_INVALID_ARG, "workgroup too small for a %d-vertex mesh", c.N);
+  if (in[0] == 1024 && (b->fp64 || c.N > 3072))
+    return fail(NPFEM_ERR_INVALID_ARG,
+                "1024-thread local steps take FP32 state and meshes of at most 3072 vertices");
   int tile = -1;
   for (int t = 0; t < gemm_num_tiles(b->gemm_kind); ++t) {
     int bm, bn;

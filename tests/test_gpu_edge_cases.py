@@ -107,3 +107,44 @@ def test_run_as_one_launch_equals_steps(prec):
         b2.run(f2, s.dt, s.n_iter, 0)
     b1.close()
     b2.close()
+
+
+@pytest.mark.parametrize("stiff", [False, True])
+def test_local_block_1024(stiff):
+    """1024-thread local steps pinned for every class of an uneven batch
+    (RBCs and platelets with two vertices per thread, 2562-vertex cells with
+    three, the large mesh's elements in two LDS chunks), FP32, 3 steps x 3
+    iterations; cells of every class against the oracle."""
+    import torch
+    from paper_2011_04332_amd import solver
+    s = W.uneven(n_rbc=4, n_plt=3, n_large=2, n_steps=3, n_iter=3)
+    if stiff:
+        s = W.stiff(s)
+    s = as_precision(s, np.float32)
+    log(f"local block 1024 stiff={stiff}")
+    b, pos, vel, f, _ = solver.batch_from_suspension(s, precision="fp32")
+    for k in range(len(s.classes)):
+        b.set_config(k, (1024, 64, 64, -1))
+    for _ in range(s.n_steps):
+        b.step(f, s.dt, s.n_iter)
+    b.sync_status()
+    torch.cuda.synchronize()
+    assert all(b.config(k)[0] == 1024 for k in range(len(s.classes)))
+    x = pos.double().cpu().numpy()
+    b.close()
+    cells = [0, 3, 4, 6, 7, 8]
+    err = max_error(s, x, oracle_cells(s, cells))
+    log(f"local block 1024 stiff={stiff} err {err:.3e}")
+    assert err <= TOL["fp32"]
+
+
+def test_local_block_1024_refused_for_fp64():
+    """The 1024-thread local step exists for FP32 state only."""
+    from paper_2011_04332_amd import _lib, solver
+    s = W.uneven(n_rbc=2, n_plt=1, n_large=0, n_steps=1)
+    b, _, _, _, _ = solver.batch_from_suspension(s, precision="fp64")
+    try:
+        with pytest.raises(_lib.NpfemError, match="1024"):
+            b.set_config(0, (1024, 64, 64, -1))
+    finally:
+        b.close()
