@@ -87,7 +87,10 @@ typedef struct npfem_material {
 
 #define NPFEM_OPT_ENERGY 1u     /* record per-cell FP64 energy of every PD iterate of the last step */
 #define NPFEM_OPT_NO_GRAPH 2u   /* launch kernels one by one instead of replaying a captured hipGraph */
-#define NPFEM_OPT_AUTOTUNE 4u   /* time candidate tile shapes per mesh class at the first step */
+#define NPFEM_OPT_AUTOTUNE 4u   /* time candidate launch shapes per mesh class at the first
+                                   step; FP32 batches of several classes also time whole
+                                   steps (from a saved and restored state) with a
+                                   1024-thread local step for meshes of 1537-3072 vertices */
 #define NPFEM_OPT_SYNC_CHECK 8u /* npfem_step synchronises and reports NONFINITE itself */
 #define NPFEM_OPT_KERNEL_TIMING 16u /* launch one by one with a HIP event pair around every
                                        kernel; read with npfem_kernel_times */

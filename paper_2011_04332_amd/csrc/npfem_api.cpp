@@ -1509,6 +1509,91 @@ int npfem_create_batch(const npfem_mesh* meshes, int32_t n_meshes, const int32_t
   return NPFEM_OK;
 }
 
+// Whole-step trial of the 1024-thread local step for large meshes (FP32
+// state, several mesh classes). The autotuner times each class alone, but a
+// 1024-thread workgroup's cost depends on the other classes' branches that
+// run beside it (it waits longer for a CU with 16 free wave slots), so this
+// choice is made on whole steps with the class branches forked as in the
+// captured graph: launched eagerly from the state saved here, which is
+// restored after every trial.
+static int joint_tune(npfem_batch_s* b, const void* forces, double h, int n_iter) {
+  if (b->fp64 || b->qn_hist >= 0 || (b->flags & NPFEM_OPT_KERNEL_TIMING)) return NPFEM_OK;
+  int active = 0;
+  std::vector<int> cand;
+  for (size_t k = 0; k < b->cls.size(); ++k) {
+    const ClassState& c = b->cls[k];
+    if (c.n_cells == 0) continue;
+    ++active;
+    if (c.N > 1536 && c.N <= 3072 && c.local_block != 1024 &&
+        local_prepare<float>(slice_of<float>(c).cv, 1024) == hipSuccess)
+      cand.push_back((int)k);
+  }
+  hipGetLastError();
+  if (active < 2 || cand.empty()) return NPFEM_OK;
+  hipStream_t st = b->stream;
+  const size_t bytes = sizeof(float) * 3 * (size_t)b->sumN;
+  void* sx = nullptr;
+  void* sv = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto release = [&]() {
+    if (sx) hipFree(sx);
+    if (sv) hipFree(sv);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  };
+  hipError_t e = hipMalloc(&sx, bytes);
+  if (e == hipSuccess) e = hipMalloc(&sv, bytes);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipMemcpyAsync(sx, b->pos, bytes, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(sv, b->vel, bytes, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) {
+    release();
+    return hip_fail(e, "joint tuning");
+  }
+  auto restore = [&]() {
+    hipError_t r = hipMemcpyAsync(b->pos, sx, bytes, hipMemcpyDeviceToDevice, st);
+    if (r == hipSuccess) r = hipMemcpyAsync(b->vel, sv, bytes, hipMemcpyDeviceToDevice, st);
+    return r;
+  };
+  // one warm-up step, then the best of three timed steps
+  auto step_ms = [&](float* best) -> int {
+    int rc = prepare_kernels(b);
+    if (!rc) rc = enqueue_any(b, forces, h, n_iter, st, true);
+    if (rc) return rc;
+    *best = 1e30f;
+    for (int r = 0; r < 3; ++r) {
+      hipError_t x = restore();
+      if (x == hipSuccess) x = hipEventRecord(e0, st);
+      if (x != hipSuccess) return hip_fail(x, "joint tuning");
+      if ((rc = enqueue_any(b, forces, h, n_iter, st, true))) return rc;
+      float ms = 0.f;
+      x = hipEventRecord(e1, st);
+      if (x == hipSuccess) x = hipEventSynchronize(e1);
+      if (x == hipSuccess) x = hipEventElapsedTime(&ms, e0, e1);
+      if (x != hipSuccess) return hip_fail(x, "joint tuning");
+      *best = std::min(*best, ms);
+    }
+    return NPFEM_OK;
+  };
+  int rc = NPFEM_OK;
+  for (int k : cand) {
+    ClassState& c = b->cls[k];
+    const int keep = c.local_block;
+    float t_keep = 0.f, t_wide = 0.f;
+    if ((rc = step_ms(&t_keep))) break;
+    c.local_block = 1024;
+    if ((rc = step_ms(&t_wide))) break;
+    if (!(t_wide < t_keep)) c.local_block = keep;
+  }
+  e = restore();
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  release();
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(e, "joint tuning");
+  return prepare_kernels(b);
+}
+
 // Argument checks, refactorisation on a new dt and the energy record's
 // size, shared by npfem_step and npfem_run (b checked, device current).
 static int step_prepare(npfem_batch b, const void* ext_forces, double dt, int32_t n_iter) {
@@ -1521,12 +1606,14 @@ static int step_prepare(npfem_batch b, const void* ext_forces, double dt, int32_
         return fail(NPFEM_ERR_INVALID_ARG,
                     "the quasi-Newton step covers the undamped, contact-free objective");
   int rc;
+  bool tuned_now = false;
   if (dt != b->dt) {
     HIP_TRY(hipStreamSynchronize(b->stream), "sync before refactorisation");
     if ((rc = factorise(b, dt))) return rc;
     if ((b->flags & NPFEM_OPT_AUTOTUNE) && !b->tuned) {
       if ((rc = b->fp64 ? autotune<double>(b, dt) : autotune<float>(b, dt))) return rc;
       b->tuned = true;
+      tuned_now = true;
     }
     drop_graphs(b);
   }
@@ -1544,6 +1631,8 @@ static int step_prepare(npfem_batch b, const void* ext_forces, double dt, int32_
     b->energy_cap = n_iter;
     drop_graphs(b);
   }
+  // (after the energy record is sized: the trial steps write it)
+  if (tuned_now && (rc = joint_tune(b, ext_forces, dt, n_iter))) return rc;
   return NPFEM_OK;
 }
 
