@@ -148,3 +148,33 @@ def test_local_block_1024_refused_for_fp64():
             b.set_config(0, (1024, 64, 64, -1))
     finally:
         b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_whole_step_tuning_restores_state(prec):
+    """The autotuner's whole-step trials (several classes, a 2562-vertex
+    class) run real steps from the batch's state and restore it: an
+    autotuned batch's steps equal, bitwise, those of a fresh batch pinned to
+    the configuration the tuner chose."""
+    import torch
+    from paper_2011_04332_amd import solver
+    s = as_precision(W.uneven(n_rbc=6, n_plt=4, n_large=2, n_steps=2, n_iter=3), np.float32)
+    log(f"whole-step tuning {prec}")
+    b, pos, vel, f, _ = solver.batch_from_suspension(s, precision=prec, autotune=True)
+    for _ in range(s.n_steps):
+        b.step(f, s.dt, s.n_iter)
+    b.sync_status()
+    torch.cuda.synchronize()
+    cfgs = [b.config(k) for k in range(len(s.classes))]
+    x_tuned, v_tuned = pos.clone(), vel.clone()
+    b.close()
+    b, pos, vel, f, _ = solver.batch_from_suspension(s, precision=prec)
+    for k, cfg in enumerate(cfgs):
+        b.set_config(k, (cfg[0], cfg[1], cfg[2], -1))  # sweeps: automatic, as tuned
+    for _ in range(s.n_steps):
+        b.step(f, s.dt, s.n_iter)
+    b.sync_status()
+    torch.cuda.synchronize()
+    log(f"whole-step tuning {prec}: configs {cfgs}")
+    assert torch.equal(pos, x_tuned) and torch.equal(vel, v_tuned)
+    b.close()
